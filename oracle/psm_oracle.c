@@ -1,0 +1,492 @@
+/*
+ * psm_oracle.c -- plain, slow FP64 CPU oracle of one PSM-LBM time step.
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the correctness reference for the
+ * GPU engine. Only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark may load it. It shares no code, header, table or helper with
+ * the GPU library, and the GPU library never calls it.
+ *
+ * Source: Kemmler, Rettinger, Ruede, Cuellar, Koestler, "Efficiency and
+ * scalability of fully-resolved fluid-particle simulations on heterogeneous
+ * CPU-GPU architectures" (arXiv 2303.11811).
+ *   Sec. 2.1   lattice Boltzmann method, eqs. (1)-(8)
+ *   Sec. 2.3   partially saturated cells method, eqs. (17)-(22)
+ *   Sec. 2.3.2 particle mapping (linear approximation), eqs. (25)-(27)
+ *
+ * Scheme: push form exactly as eqs. (1)-(2) are written. The state f(x,t) is
+ * the pre-collision PDF field. One step = map particles -> collide every cell
+ * (eq. 17) and accumulate force/torque (eqs. 21-22) -> stream (eq. 2).
+ *
+ * Readings where the paper is silent or ambiguous (each one is also listed in
+ * the design notes of the repository):
+ *   - D3Q19 velocity order and weights: the paper cites them only; the order
+ *     below is the canonical I/O order of this project.
+ *   - Forcing prefactor: eq. (8) is multiplied by (1 - 1/(2 tau)) (Guo et al.)
+ *     so that the momentum input per step equals f_ext, matching the half-force
+ *     velocity shift of eq. (7).
+ *   - B > 1 (overlapping particles, Sec. 2.3): every slot fraction is divided
+ *     by the cell's sum so that the total becomes exactly 1.
+ *   - At most two particles per cell (Sec. 3.1.1): keep the two largest
+ *     fractions (ties: smaller particle id), drop and count the rest, store
+ *     the kept slots in ascending particle id.
+ *   - B_i is the covered fraction itself (no tau-dependent weighting).
+ *   - Cell (i,j,k) has its centre at (i+1/2, j+1/2, k+1/2); all boxes are
+ *     periodic and every displacement uses the minimum image.
+ *   - Sub-division sampling (named in Sec. 2.3.2 as the alternative to the
+ *     linear approximation): N^3 points at offsets (k+1/2)/N - 1/2 per axis,
+ *     inclusion |s| <= r, evaluated without fused multiply-add.
+ *   - Test-only half-way bounce-back walls at z = -1/2 and z = nz - 1/2 for the
+ *     Poiseuille check (not part of the engine).
+ *
+ * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared -o libpsm_oracle.so
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NQ 19
+
+/* D3Q19 velocities and weights (Sec. 2.1; weights of Qian et al.). */
+static const int CQ[NQ][3] = {
+    {0, 0, 0},
+    {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},   {0, -1, 0},  {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},   {-1, -1, 0}, {1, -1, 0},  {-1, 1, 0},
+    {1, 0, 1},   {-1, 0, -1}, {1, 0, -1},  {-1, 0, 1},
+    {0, 1, 1},   {0, -1, -1}, {0, 1, -1},  {0, -1, 1}};
+
+static const double WQ[NQ] = {
+    1.0 / 3.0,
+    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+/* Index of the inverse direction q-bar (c_qbar = -c_q), found by search. */
+static int inverse_dir(int q)
+{
+    for (int p = 0; p < NQ; ++p)
+        if (CQ[p][0] == -CQ[q][0] && CQ[p][1] == -CQ[q][1] && CQ[p][2] == -CQ[q][2])
+            return p;
+    return -1;
+}
+
+typedef struct {
+    int nx, ny, nz;
+    double tau;
+    double fext[3];
+    int mapping;   /* 0: linear approximation, 1: sub-division sampling */
+    int nsub;      /* samples per axis for mapping == 1 */
+    int walls_z;   /* test mode: half-way bounce-back walls in z */
+} psmo_box;
+
+typedef struct {
+    int n;
+    const double *x;     /* (n,3) centre, inside [0,L) */
+    const double *r;     /* (n)   radius */
+    const double *fr;    /* (n)   f(r) of eq. (26) */
+    const double *U;     /* (n,3) translational velocity */
+    const double *Om;    /* (n,3) angular velocity */
+} psmo_particles;
+
+/* ------------------------------------------------------------------ */
+/* Lattice export for the tests.                                        */
+int psmo_lattice(int *c, double *w, int *qbar)
+{
+    for (int q = 0; q < NQ; ++q) {
+        for (int a = 0; a < 3; ++a) c[3 * q + a] = CQ[q][a];
+        w[q] = WQ[q];
+        qbar[q] = inverse_dir(q);
+    }
+    return NQ;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 2.3.2, eq. (27): V_a = integral over the unit square of
+ * sqrt(r^2 - x^2 - y^2); eq. (26): f(r) = V_a - r + 1/2.              */
+double psmo_Va(double r)
+{
+    double r2 = r * r;
+    double s = sqrt(r2 - 0.5);
+    double t1 = (1.0 / 12.0 - r2) * atan((0.5 * s) / (0.5 - r2));
+    double t2 = (1.0 / 3.0) * s;
+    double t3 = (r2 - 1.0 / 12.0) * atan(0.5 / s);
+    double t4 = (4.0 / 3.0) * r * r2 * atan(0.25 / (r * s));
+    return t1 + t2 + t3 - t4;
+}
+
+double psmo_fr(double r) { return psmo_Va(r) - r + 0.5; }
+
+/* Minimum image of one displacement component into [-L/2, L/2). */
+static double min_image(double d, double L)
+{
+    if (d >= 0.5 * L) return d - L;
+    if (d < -0.5 * L) return d + L;
+    return d;
+}
+
+static int wrap_index(int i, int n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+/* Displacement from particle centre xp to the centre of cell (i,j,k). */
+static void cell_displacement(const psmo_box *b, int i, int j, int k,
+                              const double *xp, double d[3])
+{
+    d[0] = min_image((i + 0.5) - xp[0], (double)b->nx);
+    d[1] = min_image((j + 0.5) - xp[1], (double)b->ny);
+    d[2] = min_image((k + 0.5) - xp[2], (double)b->nz);
+}
+
+/* Overlap fraction of particle p with a cell whose centre sits at d from the
+ * particle centre. Linear approximation: eps = f(r) - D with D = |d| - r
+ * (eq. 26), overlap iff eps > 0, capped at 1. Sub-division sampling: fraction
+ * of the nsub^3 sample points inside the sphere. Returns 0 for no overlap. */
+static double overlap_fraction(const psmo_box *b, const double d[3], double r, double fr)
+{
+    if (b->mapping == 0) {
+        double dist = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double eps = fr - (dist - r);
+        if (eps <= 0.0) return 0.0;
+        return eps < 1.0 ? eps : 1.0;
+    } else {
+        int n = b->nsub;
+        long inside = 0;
+        double r2 = r * r;
+        for (int kz = 0; kz < n; ++kz)
+            for (int ky = 0; ky < n; ++ky)
+                for (int kx = 0; kx < n; ++kx) {
+                    double sx = d[0] + ((kx + 0.5) / n - 0.5);
+                    double sy = d[1] + ((ky + 0.5) / n - 0.5);
+                    double sz = d[2] + ((kz + 0.5) / n - 0.5);
+                    double s2 = sx * sx + sy * sy + sz * sz;
+                    if (s2 <= r2) ++inside;
+                }
+        return (double)inside / ((double)n * n * n);
+    }
+}
+
+/* Two-slot list of one cell (Sec. 3.1.1: at most two fractions per cell). */
+typedef struct {
+    int ns;
+    int pid[2];
+    double B[2];
+} slot2;
+
+/* Candidate a is stronger than b: larger fraction, tie -> smaller id. */
+static int stronger(double Ba, int pa, double Bb, int pb)
+{
+    return Ba > Bb || (Ba == Bb && pa < pb);
+}
+
+static void slot_insert(slot2 *s, int pid, double B, long long *overflow)
+{
+    if (s->ns < 2) {
+        s->pid[s->ns] = pid;
+        s->B[s->ns] = B;
+        s->ns++;
+        return;
+    }
+    int weak = stronger(s->B[0], s->pid[0], s->B[1], s->pid[1]) ? 1 : 0;
+    if (stronger(B, pid, s->B[weak], s->pid[weak])) {
+        s->pid[weak] = pid;
+        s->B[weak] = B;
+    }
+    ++*overflow;
+}
+
+/* Ascending particle id, then B > 1 renormalisation (Sec. 2.3). */
+static void slot_finish(slot2 *s)
+{
+    if (s->ns == 2 && s->pid[0] > s->pid[1]) {
+        int tp = s->pid[0]; s->pid[0] = s->pid[1]; s->pid[1] = tp;
+        double tb = s->B[0]; s->B[0] = s->B[1]; s->B[1] = tb;
+    }
+    if (s->ns == 2) {
+        double sum = s->B[0] + s->B[1];
+        if (sum > 1.0) {
+            s->B[0] = s->B[0] / sum;
+            s->B[1] = s->B[1] / sum;
+        }
+    }
+}
+
+/* Mapping of all particles onto the box: for each particle in order, every
+ * cell of its (wrapped) bounding box [x_p - (r+1), x_p + (r+1)].          */
+static void map_all(const psmo_box *b, const psmo_particles *P, slot2 *slots,
+                    long long *overflow)
+{
+    long N = (long)b->nx * b->ny * b->nz;
+    for (long n = 0; n < N; ++n) slots[n].ns = 0;
+    for (int p = 0; p < P->n; ++p) {
+        const double *xp = P->x + 3 * p;
+        double r = P->r[p];
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = (int)floor(xp[a] - (r + 1.0));
+            hi[a] = (int)floor(xp[a] + (r + 1.0));
+        }
+        for (int kk = lo[2]; kk <= hi[2]; ++kk)
+            for (int jj = lo[1]; jj <= hi[1]; ++jj)
+                for (int ii = lo[0]; ii <= hi[0]; ++ii) {
+                    int i = wrap_index(ii, b->nx), j = wrap_index(jj, b->ny), k = wrap_index(kk, b->nz);
+                    double d[3];
+                    cell_displacement(b, i, j, k, xp, d);
+                    double B = overlap_fraction(b, d, r, P->fr[p]);
+                    if (B > 0.0)
+                        slot_insert(&slots[i + (long)b->nx * (j + (long)b->ny * k)], p, B, overflow);
+                }
+    }
+    for (long n = 0; n < N; ++n) slot_finish(&slots[n]);
+}
+
+/* ------------------------------------------------------------------ */
+/* Sec. 2.1, eq. (5): incompressible equilibrium with rho_0 = 1, c_s^2 = 1/3. */
+static double equilibrium(int q, double rho, const double V[3])
+{
+    double cv = CQ[q][0] * V[0] + CQ[q][1] * V[1] + CQ[q][2] * V[2];
+    double vv = V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
+    return WQ[q] * (rho + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
+}
+
+/* Eqs. (6)-(7): density and half-force-shifted velocity of a cell. */
+static void moments(const psmo_box *b, const double f[NQ], double *rho, double U[3])
+{
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < NQ; ++q) {
+        r += f[q];
+        for (int a = 0; a < 3; ++a) j[a] += f[q] * CQ[q][a];
+    }
+    *rho = r;
+    for (int a = 0; a < 3; ++a) U[a] = j[a] + 0.5 * b->fext[a];
+}
+
+static void cross(const double a[3], const double c[3], double out[3])
+{
+    out[0] = a[1] * c[2] - a[2] * c[1];
+    out[1] = a[2] * c[0] - a[0] * c[2];
+    out[2] = a[0] * c[1] - a[1] * c[0];
+}
+
+/* Collision of one cell, eqs. (3), (8), (17)-(22).
+ * f:  pre-collision PDFs; ft: post-collision PDFs (output).
+ * ns slots with particle ids pid[] and fractions B[] (already renormalised).
+ * g (ns x 3, optional): sum_q C^solid_{q,s} c_qbar of each slot, the per-cell
+ * factor of eqs. (21)-(22). d (ns x 3, optional): cell-centre lever arm.    */
+static void collide_cell(const psmo_box *b, int i, int j, int k, const double f[NQ],
+                         int ns, const int *pid, const double *Bs,
+                         const psmo_particles *P, double ft[NQ], double *g, double *dout)
+{
+    double rho, U[3];
+    moments(b, f, &rho, U);
+    double tau = b->tau;
+
+    double Btot = 0.0;
+    for (int s = 0; s < ns; ++s) Btot += Bs[s];
+
+    /* Solid collision operators per slot, eq. (19); particle velocity at the
+     * cell centre, eq. (20). */
+    double Csol[2][NQ];
+    double dvec[2][3];
+    for (int s = 0; s < ns; ++s) {
+        int p = pid[s];
+        cell_displacement(b, i, j, k, P->x + 3 * p, dvec[s]);
+        double w_x_d[3], V[3];
+        cross(P->Om + 3 * p, dvec[s], w_x_d);
+        for (int a = 0; a < 3; ++a) V[a] = P->U[3 * p + a] + w_x_d[a];
+        for (int q = 0; q < NQ; ++q) {
+            int qb = inverse_dir(q);
+            Csol[s][q] = (f[qb] - equilibrium(qb, rho, U)) - (f[q] - equilibrium(q, rho, V));
+        }
+    }
+
+    double pref = 1.0 - 1.0 / (2.0 * tau);
+    for (int q = 0; q < NQ; ++q) {
+        /* eq. (3) with Delta t = 1 */
+        double Csrt = (equilibrium(q, rho, U) - f[q]) / tau;
+        /* eq. (8), Guo prefactor (1 - 1/(2 tau)), c_s^2 = 1/3, c_s^4 = 1/9 */
+        double cu = CQ[q][0] * U[0] + CQ[q][1] * U[1] + CQ[q][2] * U[2];
+        double Fq = 0.0;
+        for (int a = 0; a < 3; ++a)
+            Fq += (3.0 * (CQ[q][a] - U[a]) + 9.0 * cu * CQ[q][a]) * b->fext[a];
+        Fq = pref * WQ[q] * Fq;
+        /* eqs. (17)-(18) */
+        double sol = 0.0;
+        for (int s = 0; s < ns; ++s) sol += Bs[s] * Csol[s][q];
+        ft[q] = f[q] + (1.0 - Btot) * Csrt + sol + (1.0 - Btot) * Fq;
+    }
+
+    /* Per-slot factor of eqs. (21)-(22): sum_q C^solid_q c_qbar = -sum_q C^solid_q c_q. */
+    for (int s = 0; s < ns; ++s) {
+        double gs[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < NQ; ++q)
+            for (int a = 0; a < 3; ++a) gs[a] -= Csol[s][q] * CQ[q][a];
+        if (g)
+            for (int a = 0; a < 3; ++a) g[3 * s + a] = gs[a];
+        if (dout)
+            for (int a = 0; a < 3; ++a) dout[3 * s + a] = dvec[s][a];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Public oracle entry points (called from Python through ctypes).      */
+
+static psmo_particles make_particles(int n, const double *x, const double *r, const double *fr,
+                                     const double *U, const double *Om)
+{
+    psmo_particles P = {n, x, r, fr, U, Om};
+    return P;
+}
+
+/* Equilibrium initialisation f_q = E_q(rho, u) (eq. 5). rho may be NULL (=1).
+ * u is [3][N]. f is [19][N]. */
+void psmo_equilibrium_field(const psmo_box *b, const double *rho, const double *u, double *f)
+{
+    long N = (long)b->nx * b->ny * b->nz;
+    for (long n = 0; n < N; ++n) {
+        double V[3] = {u[n], u[N + n], u[2 * N + n]};
+        double r = rho ? rho[n] : 1.0;
+        for (int q = 0; q < NQ; ++q) f[q * N + n] = equilibrium(q, r, V);
+    }
+}
+
+/* Density and velocity (eqs. 6-7) of a [19][N] field. */
+void psmo_macroscopic(const psmo_box *b, const double *f, double *rho, double *u)
+{
+    long N = (long)b->nx * b->ny * b->nz;
+    for (long n = 0; n < N; ++n) {
+        double fc[NQ], r, U[3];
+        for (int q = 0; q < NQ; ++q) fc[q] = f[q * N + n];
+        moments(b, fc, &r, U);
+        rho[n] = r;
+        for (int a = 0; a < 3; ++a) u[a * N + n] = U[a];
+    }
+}
+
+/* Mapping only: B [2][N] and pid [2][N] (-1 = empty slot). Returns the number
+ * of dropped (cell, particle) overlaps. */
+long long psmo_map(const psmo_box *b, int np, const double *x, const double *r, const double *fr,
+                   double *B, int *pid)
+{
+    long N = (long)b->nx * b->ny * b->nz;
+    psmo_particles P = make_particles(np, x, r, fr, NULL, NULL);
+    slot2 *slots = (slot2 *)malloc(sizeof(slot2) * (size_t)N);
+    long long overflow = 0;
+    map_all(b, &P, slots, &overflow);
+    for (long n = 0; n < N; ++n) {
+        for (int s = 0; s < 2; ++s) {
+            B[s * N + n] = s < slots[n].ns ? slots[n].B[s] : 0.0;
+            pid[s * N + n] = s < slots[n].ns ? slots[n].pid[s] : -1;
+        }
+    }
+    free(slots);
+    return overflow;
+}
+
+/* Slots of a single cell by brute force over every particle (same rules as
+ * psmo_map, used to check sampled cells of large boxes). Returns ns. */
+int psmo_map_cell(const psmo_box *b, int i, int j, int k, int np, const double *x,
+                  const double *r, const double *fr, int *pid2, double *B2, long long *overflow)
+{
+    slot2 s;
+    s.ns = 0;
+    long long ov = 0;
+    for (int p = 0; p < np; ++p) {
+        double d[3];
+        cell_displacement(b, i, j, k, x + 3 * p, d);
+        double B = overlap_fraction(b, d, r[p], fr[p]);
+        if (B > 0.0) slot_insert(&s, p, B, &ov);
+    }
+    slot_finish(&s);
+    for (int t = 0; t < 2; ++t) {
+        pid2[t] = t < s.ns ? s.pid[t] : -1;
+        B2[t] = t < s.ns ? s.B[t] : 0.0;
+    }
+    if (overflow) *overflow = ov;
+    return s.ns;
+}
+
+/* Collision of one cell with explicit slots (for sampled checks).
+ * g (ns x 3) receives sum_q C^solid c_qbar per slot. */
+void psmo_collide_cell(const psmo_box *b, int i, int j, int k, const double *f19, int ns,
+                       const int *pid, const double *Bs, int np, const double *x,
+                       const double *U, const double *Om, double *ft19, double *g)
+{
+    psmo_particles P = make_particles(np, x, NULL, NULL, U, Om);
+    collide_cell(b, i, j, k, f19, ns, pid, Bs, &P, ft19, g, NULL);
+}
+
+/* nsteps full time steps on f ([19][N], pre-collision, in/out).
+ * Outputs of the LAST step: F, T (np,3) by eqs. (21)-(22) accumulated in cell
+ * order; Ascale (np) = sum over cells and slots of B_s |g_s| (the magnitude
+ * scale of the force sum); B/pid [2][N] slots of the last mapping (optional).
+ * Returns the total slot overflow count of the last step's mapping. */
+long long psmo_run(const psmo_box *b, int nsteps, int np, const double *x, const double *r,
+                   const double *fr, const double *U, const double *Om, double *f,
+                   double *F, double *T, double *Ascale, double *Bout, int *pidout)
+{
+    int nx = b->nx, ny = b->ny, nz = b->nz;
+    long N = (long)nx * ny * nz;
+    psmo_particles P = make_particles(np, x, r, fr, U, Om);
+    slot2 *slots = (slot2 *)malloc(sizeof(slot2) * (size_t)N);
+    double *fnew = (double *)malloc(sizeof(double) * (size_t)NQ * (size_t)N);
+    long long overflow = 0;
+
+    for (int step = 0; step < nsteps; ++step) {
+        overflow = 0;
+        map_all(b, &P, slots, &overflow);
+        for (int p = 0; p < np; ++p) {
+            for (int a = 0; a < 3; ++a) { F[3 * p + a] = 0.0; T[3 * p + a] = 0.0; }
+            if (Ascale) Ascale[p] = 0.0;
+        }
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    long n = i + (long)nx * (j + (long)ny * k);
+                    double fc[NQ], ft[NQ], g[6], d[6];
+                    for (int q = 0; q < NQ; ++q) fc[q] = f[q * N + n];
+                    slot2 *s = &slots[n];
+                    collide_cell(b, i, j, k, fc, s->ns, s->pid, s->B, &P, ft, g, d);
+                    /* eqs. (21)-(22) with Delta x = Delta t = 1 */
+                    for (int t = 0; t < s->ns; ++t) {
+                        int p = s->pid[t];
+                        double Bg[3], tq[3];
+                        for (int a = 0; a < 3; ++a) Bg[a] = s->B[t] * g[3 * t + a];
+                        cross(d + 3 * t, Bg, tq);
+                        for (int a = 0; a < 3; ++a) {
+                            F[3 * p + a] += Bg[a];
+                            T[3 * p + a] += tq[a];
+                        }
+                        if (Ascale)
+                            Ascale[p] += s->B[t] * sqrt(g[3 * t] * g[3 * t] + g[3 * t + 1] * g[3 * t + 1] +
+                                                        g[3 * t + 2] * g[3 * t + 2]);
+                    }
+                    /* eq. (2): f_q(x + c_q, t + 1) = ft_q(x, t) */
+                    for (int q = 0; q < NQ; ++q) {
+                        int ii = i + CQ[q][0], jj = j + CQ[q][1], kk = k + CQ[q][2];
+                        if (b->walls_z && (kk < 0 || kk >= nz)) {
+                            /* half-way bounce-back at a resting wall (test mode) */
+                            fnew[inverse_dir(q) * N + n] = ft[q];
+                            continue;
+                        }
+                        ii = wrap_index(ii, nx);
+                        jj = wrap_index(jj, ny);
+                        kk = wrap_index(kk, nz);
+                        fnew[q * N + ii + (long)nx * (jj + (long)ny * kk)] = ft[q];
+                    }
+                }
+        memcpy(f, fnew, sizeof(double) * (size_t)NQ * (size_t)N);
+    }
+
+    if (Bout && pidout) {
+        for (long n = 0; n < N; ++n)
+            for (int t = 0; t < 2; ++t) {
+                Bout[t * N + n] = t < slots[n].ns ? slots[n].B[t] : 0.0;
+                pidout[t * N + n] = t < slots[n].ns ? slots[n].pid[t] : -1;
+            }
+    }
+    free(fnew);
+    free(slots);
+    return overflow;
+}

@@ -1,0 +1,194 @@
+"""Pins of the oracle's lattice Boltzmann part (Sec. 2.1, eqs. 1-8) against
+closed forms, exact invariants and a textbook LBM written independently here.
+
+Readings exercised: the forcing prefactor (1 - 1/(2 tau)) of eq. (8), and the
+half-way bounce-back wall used only by the Poiseuille check."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_11811_amd import inputs
+
+
+def _total_momentum(box, f):
+    c, _, _ = oracle.lattice()
+    return (f.T @ c.astype(float)).sum(axis=0)
+
+
+def test_uniform_flow_is_a_fixed_point():
+    box = oracle.Box(6, 5, 4, tau=0.8)
+    U0 = np.array([0.02, -0.01, 0.005])
+    u = np.repeat(U0[:, None], box.N, axis=1)
+    f0 = oracle.equilibrium(box, u)
+    res = oracle.run(box, f0, 10)
+    assert np.max(np.abs(res.f - f0)) < 2e-16
+
+
+@pytest.mark.parametrize("tau", [0.51, 0.8, 1.7])
+def test_mass_and_momentum_conserved(tau):
+    spec = inputs.random_small((9, 7, 6), 0, (2, 3), seed=5, tau=tau)
+    box = oracle.Box(*spec.dims, tau=tau)
+    f0 = oracle.equilibrium(box, spec.u0, spec.rho0)
+    f0 += np.random.default_rng(1).normal(0, 1e-4, f0.shape)  # non-equilibrium start
+    res = oracle.run(box, f0, 50)
+    assert abs(res.f.sum() - f0.sum()) / f0.sum() < 1e-13
+    P0, P1 = _total_momentum(box, f0), _total_momentum(box, res.f)
+    assert np.max(np.abs(P1 - P0)) < 1e-13 * box.N
+
+
+@pytest.mark.parametrize("tau", [0.55, 0.8, 1.3])
+def test_uniform_force_from_rest(tau):
+    # The momentum input per step must equal the force density: j(t) = t f.
+    g = np.array([1e-4, -3e-5, 2e-5])
+    box = oracle.Box(4, 4, 4, tau=tau, fext=tuple(g))
+    f = oracle.equilibrium(box, np.zeros((3, box.N)))
+    for t in range(1, 6):
+        f = oracle.run(box, f, 1).f
+        rho, u = oracle.macroscopic(box, f)
+        j = u - 0.5 * g[:, None]
+        assert np.allclose(j, t * g[:, None], rtol=0, atol=1e-15 * t)
+        assert np.allclose(rho, 1.0, atol=1e-15)
+
+
+def _amplitude(box, f, comp, k_axis):
+    _, u = oracle.macroscopic(box, f)
+    dims = (box.nx, box.ny, box.nz)
+    L = dims[k_axis]
+    coord = np.arange(L) + 0.5
+    ucomp = u[comp].reshape(box.nz, box.ny, box.nx)
+    prof = ucomp.mean(axis=tuple(a for a in range(3) if a != 2 - k_axis))
+    return 2.0 / L * np.sum(prof * np.sin(2 * math.pi * coord / L))
+
+
+def _shear_rate_error(tau, L, axis_u, axis_k):
+    dims = [1, 1, 1]
+    dims[axis_k] = L
+    box = oracle.Box(*dims, tau=tau)
+    f = oracle.equilibrium(box, inputs.shear_wave(tuple(dims), 1e-4, axis_u=axis_u, axis_k=axis_k))
+    nu = (tau - 0.5) / 3.0
+    k = 2 * math.pi / L
+    T = int(2.0 / (nu * k * k))
+    f = oracle.run(box, f, T // 2).f
+    a1 = _amplitude(box, f, axis_u, axis_k)
+    f = oracle.run(box, f, T // 2).f
+    a2 = _amplitude(box, f, axis_u, axis_k)
+    rate = -math.log(a2 / a1) / (T // 2)
+    return rate / (nu * k * k) - 1.0
+
+
+@pytest.mark.parametrize("tau,axes", [(0.6, (0, 1)), (0.9, (2, 0)), (0.75, (1, 2))])
+def test_shear_wave_decay_rate(tau, axes):
+    """u_a = A sin(k x_b) decays as exp(-nu k^2 t), nu = (tau - 1/2)/3 (eq. 4),
+    up to a lattice error O(k^2): within 1e-3 at L = 64, and the error falls
+    by 4x when L doubles (second order)."""
+    e32 = _shear_rate_error(tau, 32, *axes)
+    e64 = _shear_rate_error(tau, 64, *axes)
+    assert abs(e64) < 1e-3
+    assert 3.8 < e32 / e64 < 4.2
+
+
+def test_taylor_green_decay_rate():
+    # 2-D Taylor-Green vortex: velocity amplitude decays as exp(-2 nu k^2 t)
+    L, tau = 32, 0.6
+    box = oracle.Box(L, L, 2, tau=tau)
+    f = oracle.equilibrium(box, inputs.taylor_green((L, L, 2), 0.01))
+
+    def amp(f):
+        _, u = oracle.macroscopic(box, f)
+        ref = inputs.taylor_green((L, L, 2), 1.0)
+        return float((u[0] * ref[0]).sum() / (ref[0] * ref[0]).sum())
+
+    T = 600
+    f = oracle.run(box, f, T // 2).f
+    a1 = amp(f)
+    f = oracle.run(box, f, T // 2).f
+    a2 = amp(f)
+    nu = (tau - 0.5) / 3.0
+    k = 2 * math.pi / L
+    rate = -math.log(a2 / a1) / (T // 2)
+    assert abs(rate / (2 * nu * k * k) - 1.0) < 1e-3
+
+
+@pytest.mark.parametrize("tau", [0.55, 0.8, 1.0, 0.5 + math.sqrt(3.0) / 4.0])
+def test_poiseuille_halfway_bounce_back(tau):
+    """Body-force-driven channel between half-way bounce-back walls at z = -1/2
+    and z = H - 1/2. The BGK steady state is the parabola with walls at the
+    half-way points plus a uniform slip (2g/(3 nu))((tau - 1/2)^2 - 3/16),
+    which vanishes at tau = 1/2 + sqrt(3)/4."""
+    H, g = 12, 1e-5
+    box = oracle.Box(2, 2, H, tau=tau, fext=(g, 0.0, 0.0), walls_z=True)
+    f = oracle.equilibrium(box, np.zeros((3, box.N)))
+    nu = (tau - 0.5) / 3.0
+    nsteps = int(40 * H * H / (math.pi ** 2 * nu)) + 200
+    f = oracle.run(box, f, nsteps).f
+    _, u = oracle.macroscopic(box, f)
+    z = np.arange(H) + 0.0
+    exact = g / (2 * nu) * (z + 0.5) * (H - 0.5 - z) + 2 * g / (3 * nu) * ((tau - 0.5) ** 2 - 3.0 / 16.0)
+    prof = u[0].reshape(H, 2, 2)[:, 0, 0]
+    assert np.max(np.abs(prof - exact)) / exact.max() < 1e-9
+
+
+def test_streaming_moves_mass_along_momentum():
+    """sum_x x (rho(x,t+1) - 1) - sum_x x (rho(x,t) - 1) = sum_x j(x,t) exactly
+    for a localized perturbation (eq. 2 pushes f_q along +c_q)."""
+    L = 24
+    box = oracle.Box(L, L, L, tau=0.7)
+    c = (np.arange(L) + 0.5)
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    r2 = (X - 12) ** 2 + (Y - 12) ** 2 + (Z - 12) ** 2
+    # compact support (radius 5): nothing reaches the periodic seam in 3 steps
+    bump = (np.maximum(0.0, 1.0 - r2 / 25.0) ** 3).ravel()
+    rho = 1 + 0.01 * bump
+    u = np.stack([0.03 * bump, -0.02 * bump, 0.01 * bump])
+    f = oracle.equilibrium(box, u, rho)
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
+    for _ in range(3):
+        rho0, u0 = oracle.macroscopic(box, f)
+        m0 = pos @ (rho0 - 1)
+        P = u0.sum(axis=1)  # no force: U = j
+        f = oracle.run(box, f, 1).f
+        rho1, _ = oracle.macroscopic(box, f)
+        m1 = pos @ (rho1 - 1)
+        assert np.allclose(m1 - m0, P, rtol=1e-10, atol=1e-13)
+        assert np.abs(P).max() > 1e-3
+
+
+def _textbook_lbm_step(f, dims, tau, g):
+    """Plain BGK D3Q19 with Guo forcing and incompressible equilibrium, streamed
+    with np.roll. Written independently of the oracle (vectorised numpy)."""
+    nx, ny, nz = dims
+    cs = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+                   [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1],
+                   [1, 0, -1], [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]])
+    ws = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    F = f.reshape(19, nz, ny, nx)
+    rho = F.sum(axis=0)
+    jv = np.einsum("qa,qzyx->azyx", cs.astype(float), F)
+    U = jv + 0.5 * np.asarray(g)[:, None, None, None]
+    cu = np.einsum("qa,azyx->qzyx", cs.astype(float), U)
+    uu = (U * U).sum(axis=0)
+    feq = ws[:, None, None, None] * (rho[None] + 3 * cu + 4.5 * cu ** 2 - 1.5 * uu[None])
+    cg = cs.astype(float) @ np.asarray(g)
+    ug = np.einsum("a,azyx->zyx", np.asarray(g), U)
+    Fq = (1 - 0.5 / tau) * ws[:, None, None, None] * (3 * (cg[:, None, None, None] - ug[None])
+                                                        + 9 * cu * cg[:, None, None, None])
+    post = F + (feq - F) / tau + Fq
+    out = np.empty_like(post)
+    for q in range(19):
+        out[q] = np.roll(post[q], shift=(cs[q, 2], cs[q, 1], cs[q, 0]), axis=(0, 1, 2))
+    return out.reshape(19, -1)
+
+
+def test_no_particles_equals_textbook_lbm():
+    dims, tau, g = (8, 6, 5), 0.63, (2e-5, -1e-5, 3e-6)
+    spec = inputs.random_small(dims, 0, (2, 3), seed=9, tau=tau)
+    box = oracle.Box(*dims, tau=tau, fext=g)
+    f = oracle.equilibrium(box, spec.u0, spec.rho0)
+    f += np.random.default_rng(2).normal(0, 1e-4, f.shape)
+    ref = f.copy()
+    for _ in range(5):
+        ref = _textbook_lbm_step(ref, dims, tau, g)
+    got = oracle.run(box, f, 5).f
+    assert np.max(np.abs(got - ref)) < 1e-15

@@ -1,0 +1,278 @@
+#!/usr/bin/env python
+"""PSM-LBM benchmark on one MI355X.
+
+Workload (default): 512^3 periodic box, FP64 PDFs, tau 0.55, body force
+1e-6 along +x, 3204 seeded non-overlapping spheres of diameter 20 (10 %
+solid volume fraction) with velocities in [-0.005, 0.005]^3. One timed
+step is the whole coupled hot path of the paper's GPU time step: upload the
+sphere table (positions, radii, f(r), velocities) and rebuild the per-tile
+candidate lists, run the fused mapping + stream-collide + force/torque
+launch and the per-sphere reduction, and read the forces and torques back.
+
+Prints one JSON line. `value` is MLUPS (cells x steps / wall time / 1e6)
+with the PDFs resident in HBM. `roofline` is the step kernel's algorithmic
+PDF traffic (38 values per cell: 304 B FP64, 152 B FP32, 76 B FP16) per
+launch over its average launch time (HIP events on its own stream) against
+the 8 TB/s HBM peak. `cpu_baseline` is the FP64 oracle (single thread) on a
+bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "PSM-LBM MLUPS & % HBM roofline, FP64 vs FP32/FP16-storage at stated error"
+BYTES_PER_CELL = {0: 304, 1: 152, 2: 76}
+STORAGE_NAME = {0: "f64", 1: "f32dev", 2: "f16dev"}
+COUNTER_FILE = os.path.join(ROOT, "profiles", "k_psm_step_f64_512_counters.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("psm_kernels.hip", "psm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2303_11811_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(launch):
+    """HBM bytes per launch from committed rocprofv3 counters, if they were
+    taken on the current kernel source and launch shape."""
+    try:
+        with open(COUNTER_FILE) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_src_sha") != kernel_source_hash() or list(c.get("launch", [])) != list(launch):
+        return None
+    return c.get("hbm_bytes_per_launch")
+
+
+def run_case(psm, torch, spec, storage, steps, warmup, autotune, launch=None, full_loop=True):
+    """Time `steps` coupled steps of one box. Returns a dict of results."""
+    eng = psm.Engine([psm.desc_from_spec(spec)], storage=storage)
+    N = spec.N
+    with torch.cuda.stream(eng.stream):
+        u0 = torch.zeros((3, N), dtype=torch.float64, device=eng.device)
+    eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+    if launch is not None:
+        eng.set_launch(*launch)
+    elif autotune:
+        eng.set_equilibrium(0, u0)
+        shape, ms = eng.autotune(trial_steps=4)
+        log(f"  autotune -> {shape} {ms:.3f} ms/step")
+    eng.set_equilibrium(0, u0)
+    del u0
+
+    def one_step():
+        if full_loop:
+            eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+        eng.step(1)
+        if full_loop:
+            eng.get_forces(0)
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    eng.reset_timing()
+    eng.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step()
+    eng.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_launch, kern_ms = eng.get_timing()
+    eng.set_timing(False)
+    mass, mom, ov = eng.get_stats(0)
+    res = dict(ms_per_step=(t1 - t0) * 1e3 / steps, mlups=N * steps / (t1 - t0) / 1e6,
+               kernel_ms=kern_ms / max(n_launch, 1), launches=n_launch, launch=list(eng.get_launch()),
+               mass=mass, slot_overflows=ov)
+    eng.close()
+    del eng
+    torch.cuda.empty_cache()
+    return res
+
+
+def stream_copy_gbps(psm, torch, nbytes=4 << 30, reps=20):
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        psm.psm_stream_copy(a.data_ptr(), b.data_ptr(), nbytes, s.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        psm.psm_stream_copy(a.data_ptr(), b.data_ptr(), nbytes, s.cuda_stream)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def precision_errors(psm, torch, inputs, n=64, steps=1000):
+    """L2 velocity error and max relative force error of the deviation
+    storage forms against the FP64 path on an n^3 copy of the workload."""
+    import numpy as np
+
+    spec = inputs.paper_scale(n=n, seed=1)
+    out = {}
+    ref = None
+    for st in (0, 1, 2):
+        eng = psm.Engine([psm.desc_from_spec(spec)], storage=st)
+        eng.set_equilibrium(0, np.zeros((3, spec.N)))
+        eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+        eng.step(steps)
+        _, u = eng.get_macroscopic(0)
+        F, _ = eng.get_forces(0)
+        u = u.cpu().numpy()
+        eng.close()
+        if st == 0:
+            ref = (u, F)
+            continue
+        l2 = float(np.linalg.norm(u - ref[0]) / np.linalg.norm(ref[0]))
+        fe = float(np.max(np.linalg.norm(F - ref[1], axis=1) / np.linalg.norm(ref[1], axis=1)))
+        out[STORAGE_NAME[st]] = {"l2_u_rel": l2, "max_force_rel": fe}
+    return out
+
+
+def cpu_baseline(inputs, n, steps):
+    import numpy as np
+    import oracle
+
+    oracle.build(force=False)
+    spec = inputs.paper_scale(n=n, seed=1)
+    box = oracle.Box(*spec.dims, tau=spec.tau, fext=spec.fext)
+    f0 = oracle.equilibrium(box, np.zeros((3, spec.N)))
+    t0 = time.perf_counter()
+    oracle.run(box, f0, steps, spec.x, spec.r, spec.U, spec.Om)
+    dt = time.perf_counter() - t0
+    return {"value": spec.N * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{n}^3 periodic box with the same sphere size, solid fraction (0.10, "
+                      f"{len(spec.r)} spheres), tau and body force, {steps} FP64 steps, "
+                      f"single-threaded C oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--launch", type=str, default=None, help="tx,ty,tz (skips the autotuner)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--kernel-only", action="store_true", help="time psm_step alone (no upload/readback)")
+    ap.add_argument("--precision-steps", type=int, default=200)
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-size", type=int, default=128)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (one box per GPU would "
+              "shard by domain decomposition; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2303_11811_amd as psm
+    from paper_2303_11811_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    psm.lib()
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+
+    spec = inputs.paper_scale(n=args.size, seed=1)
+    log(f"workload: {args.size}^3, {len(spec.r)} spheres, tau {spec.tau}, g {spec.fext[0]}")
+
+    log("FP64 main run")
+    main_res = run_case(psm, torch, spec, 0, args.steps, args.warmup, not args.no_autotune, launch,
+                        full_loop=not args.kernel_only)
+    log(f"  {main_res}")
+
+    forms = {}
+    if not args.no_precision:
+        for st in (1, 2):
+            log(f"{STORAGE_NAME[st]} run")
+            r = run_case(psm, torch, spec, st, args.precision_steps, 10, not args.no_autotune, None,
+                         full_loop=not args.kernel_only)
+            r["roofline_frac"] = spec.N * BYTES_PER_CELL[st] / (r["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS
+            forms[STORAGE_NAME[st]] = {"mlups": r["mlups"], "ms_per_step": r["ms_per_step"],
+                                       "kernel_ms": r["kernel_ms"], "launch": r["launch"],
+                                       "roofline_frac": r["roofline_frac"],
+                                       "speedup_vs_f64": r["mlups"] / main_res["mlups"]}
+            log(f"  {forms[STORAGE_NAME[st]]}")
+        log("precision errors (64^3 copy, 1000 steps, vs the FP64 path)")
+        err = precision_errors(psm, torch, inputs)
+        for k, v in err.items():
+            forms[k]["error_vs_f64_64cubed_1000steps"] = v
+        log(f"  {err}")
+
+    log("stream copy")
+    copy_gbps = stream_copy_gbps(psm, torch)
+    log(f"  {copy_gbps:.0f} GB/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(inputs, args.cpu_size, args.cpu_steps)
+        log(f"  {cpu}")
+
+    algo_bytes = spec.N * BYTES_PER_CELL[0]
+    achieved = algo_bytes / (main_res["kernel_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(main_res["launch"])
+    out = {
+        "metric": METRIC,
+        "value": round(main_res["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"PSM-LBM D3Q19 SRT, {args.size}^3 periodic, FP64, tau 0.55, body force 1e-6 +x, "
+                        f"{len(spec.r)} spheres d=20 (10% solid), mapping + force/torque every step",
+            "cells": spec.N, "spheres": int(len(spec.r)), "storage": "f64",
+            "launch": main_res["launch"],
+            "step": "kernel only" if args.kernel_only else
+                    "upload spheres + bin + fused map/stream-collide/force + reduce + read forces",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": traffic,
+            "kernel": "k_psm_step<f64>", "kernel_ms": round(main_res["kernel_ms"], 4),
+            "algorithmic_bytes_per_launch": algo_bytes,
+            "frac_of_stream_copy": round(achieved / copy_gbps, 4),
+        },
+        "cpu_baseline": cpu,
+        "stream_copy_GBps": round(copy_gbps, 1),
+        "mlups_frac_of_stream_copy": round(main_res["mlups"] * 1e6 * BYTES_PER_CELL[0] / 1e9 / copy_gbps, 4),
+        "precision_forms": forms,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

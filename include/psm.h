@@ -1,0 +1,180 @@
+/*
+ * psm.h -- C ABI of the MI355X (gfx950) engine for the hot path of the
+ * partially-saturated-cells lattice Boltzmann method (PSM-LBM) of
+ * Kemmler et al., "Efficiency and scalability of fully-resolved
+ * fluid-particle simulations on heterogeneous CPU-GPU architectures"
+ * (arXiv 2303.11811).
+ *
+ * One time step (Sec. 3.1 of the paper; Fig. 4 of its GPU time loop):
+ *   sphere -> cell solid-fraction mapping (Sec. 2.3.2, eqs. 25-27),
+ *   D3Q19 SRT stream-collide with PSM coupling (Sec. 2.1 eqs. 1-8,
+ *   Sec. 2.3 eqs. 17-20), and the per-particle hydrodynamic force and
+ *   torque reduction (Sec. 2.3 eqs. 21-22).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Status: every call returns 0 (PSM_OK) or a negative PSM_E* code and never
+ *   throws. psm_last_error() returns a thread-local text of the last failure.
+ * - Argument checks happen on the host before anything is enqueued; a bad
+ *   argument returns PSM_EINVAL and leaves the context unchanged.
+ * - Lattice units: dx = dt = 1, rho_0 = 1, c_s^2 = 1/3. All boxes are periodic.
+ * - Cells: index n = x + nx*(y + ny*z); cell (i,j,k) has its centre at
+ *   (i+1/2, j+1/2, k+1/2) in [0,nx) x [0,ny) x [0,nz).
+ * - PDFs: canonical layout [19][N] (q-major), FP64, pre-collision state
+ *   f(x,t) of eq. (1). Direction order q: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z;
+ *   7..18 = (+1,+1,0),(-1,-1,0),(+1,-1,0),(-1,+1,0),(+1,0,+1),(-1,0,-1),
+ *   (+1,0,-1),(-1,0,+1),(0,+1,+1),(0,-1,-1),(0,+1,-1),(0,-1,+1).
+ *   Weights 1/3, 1/18 (axes), 1/36 (diagonals).
+ * - Ownership: the caller owns all device memory (one workspace allocation,
+ *   e.g. a torch tensor) and the HIP stream. The library owns only its kernels,
+ *   HIP graphs and a pinned host staging buffer, all released by psm_destroy.
+ * - Pointer kinds: "device" arguments are HIP device pointers and the work is
+ *   enqueued on the context's stream (asynchronous); "host" arguments are
+ *   ordinary host pointers. Calls marked "synchronises" wait for the stream.
+ * - Concurrency: calls on one context are not thread-safe. Use one context
+ *   per stream.
+ */
+#ifndef PSM_H
+#define PSM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum psm_status {
+    PSM_OK = 0,
+    PSM_EINVAL = -1,      /* invalid argument (checked on the host) */
+    PSM_EHIP = -2,        /* a HIP runtime call failed; text kept in psm_last_error */
+    PSM_ECAPACITY = -3,   /* more particles / tile candidates than the context holds */
+    PSM_ENONFINITE = -4,  /* non-finite mass or momentum found by psm_get_stats */
+    PSM_ESTATE = -6       /* call not valid in the current state */
+};
+
+/* PDF storage. FP64 stores f and computes in FP64. The deviation forms store
+ * d = f - w_q (FP16 as scale*d with a power-of-two scale) and compute the
+ * collision in FP32; forces, torques and mass sums stay FP64. */
+enum psm_storage { PSM_FP64 = 0, PSM_FP32DEV = 1, PSM_FP16DEV = 2 };
+
+/* Solid-fraction mapping (Sec. 2.3.2): the linear approximation of eq. (26),
+ * or sub-division sampling with subsample_n^3 points per cell. */
+enum psm_mapping { PSM_MAP_LINEAR = 0, PSM_MAP_SUBSAMPLE = 1 };
+
+typedef struct psm_box_desc {
+    int nx, ny, nz;         /* cells per axis, each >= 4 and >= 2*(max_radius+1)+2 */
+    double tau;             /* relaxation time, > 1/2 (eq. 3); nu = (tau-1/2)/3 (eq. 4) */
+    double fext[3];         /* body-force density f^ext (eqs. 7-8) */
+    int max_particles;      /* capacity of this box's particle table (>= 0) */
+    double max_radius;      /* largest sphere radius that will be set (>= 1) */
+    int mapping;            /* psm_mapping */
+    int subsample_n;        /* samples per axis for PSM_MAP_SUBSAMPLE (1..16) */
+} psm_box_desc;
+
+typedef struct psm_ctx psm_ctx;
+
+/* Bytes of device workspace a context over these boxes needs (host-only call).
+ * boxes: host array of nbox descriptors. bytes: host output. */
+int psm_workspace_size(const psm_box_desc* boxes, int nbox, int storage, size_t* bytes);
+
+/* Create a context. The workspace (device, >= psm_workspace_size bytes,
+ * 256-byte aligned) is carved into PDF grids, particle tables, tile lists and
+ * force partials; it must outlive the context and is not freed by it.
+ * fp16_scale: power of two used by PSM_FP16DEV (ignored otherwise; 0 selects
+ * 1024). hip_stream: hipStream_t (may be NULL for the default stream). The
+ * PDF state is undefined until psm_set_equilibrium or psm_set_pdfs. */
+int psm_create(const psm_box_desc* boxes, int nbox, int storage, double fp16_scale,
+               void* hip_stream, void* dev_workspace, size_t workspace_bytes, psm_ctx** out);
+
+/* Destroy the context (waits for its stream). Does not free the workspace. */
+int psm_destroy(psm_ctx* ctx);
+
+/* Initialise box `box` to the equilibrium of eq. (5): f_q = E_q(rho, u).
+ * rho: device [N] FP64 or NULL for rho = 1; u: device [3][N] FP64. */
+int psm_set_equilibrium(psm_ctx* ctx, int box, const double* rho, const double* u);
+
+/* Set the pre-collision PDFs f(x,t) of box `box`. f: device [19][N] FP64.
+ * Deviation storage rounds d = f - w_q to FP32 / FP16 (round to nearest even). */
+int psm_set_pdfs(psm_ctx* ctx, int box, const double* f);
+
+/* Read the pre-collision PDFs f(x,t) of box `box` into f: device [19][N] FP64. */
+int psm_get_pdfs(psm_ctx* ctx, int box, double* f);
+
+/* Read f(x,t) at ncells cells. cells: device [ncells] int cell indices (each
+ * in [0,N), else PSM_EINVAL is not detected on the device: the caller checks);
+ * out: device [19][ncells] FP64. */
+int psm_get_pdfs_at(psm_ctx* ctx, int box, int ncells, const int* cells, double* out);
+
+/* Density and velocity of eqs. (6)-(7) (U includes the f^ext/2 shift).
+ * rho: device [N] FP64; u: device [3][N] FP64. */
+int psm_get_macroscopic(psm_ctx* ctx, int box, double* rho, double* u);
+
+/* Set the spheres of box `box` (Sec. 3.1.1: positions, radii, then linear and
+ * angular velocities). Host arrays, row-major: x (n,3), r (n), U (n,3),
+ * omega (n,3) (NULL omega = 0). Positions are wrapped into the box. Radii
+ * must lie in [1, max_radius]. The library computes f(r) of eq. (26) in FP64,
+ * uploads through pinned staging and rebuilds the per-tile candidate lists;
+ * PSM_ECAPACITY if n > max_particles or a tile would list more candidates than
+ * the kernel stages (synchronises). */
+int psm_set_particles(psm_ctx* ctx, int box, int n, const double* x, const double* r,
+                      const double* U, const double* omega);
+
+/* Advance every box by nsteps time steps: per step, fused mapping +
+ * stream-collide + force/torque partial sums (one persistent launch over all
+ * boxes) and the per-particle reduction. With graphs enabled, runs of 10 steps
+ * replay a captured HIP graph. Asynchronous. */
+int psm_step(psm_ctx* ctx, int nsteps);
+
+/* Hydrodynamic force and torque of eqs. (21)-(22) on every sphere of box
+ * `box` from the last executed step. F, T: host (n,3) FP64 (n = particles set).
+ * Synchronises. Before any step: zeros. */
+int psm_get_forces(psm_ctx* ctx, int box, double* F, double* T);
+
+/* Solid fractions of the current particles (same device mapping as the step):
+ * B: device [2][N] FP64, pid: device [2][N] int (box-local particle id, -1 for
+ * an empty slot). Slots hold the two largest fractions in ascending id,
+ * renormalised to sum 1 where they exceed 1 (Sec. 2.3). */
+int psm_get_solid_fraction(psm_ctx* ctx, int box, double* B, int* pid);
+
+/* FP64 totals of the current state of box `box`: mass sum_x sum_q f,
+ * momentum sum_x sum_q f c_q (host double[3], may be NULL), and the number of
+ * dropped third-or-later overlaps of the current mapping (may be NULL).
+ * Synchronises. PSM_ENONFINITE if mass or momentum is not finite. */
+int psm_get_stats(psm_ctx* ctx, int box, double* mass, double* momentum, long long* slot_overflows);
+
+/* Launch shape of the step kernel: a tile of tx*ty threads (tx*ty == 256,
+ * tx in {16,32,64,128,256}) handling tz cells each along z. Rebuilds the tile
+ * lists (synchronises); invalidates captured graphs. */
+int psm_set_launch(psm_ctx* ctx, int tx, int ty, int tz);
+int psm_get_launch(psm_ctx* ctx, int* tx, int* ty, int* tz);
+
+/* Time every allowed launch shape on this context with HIP events
+ * (warmup + trial_steps steps each), keep the fastest and report it.
+ * The trial steps advance and overwrite the PDF state: set the state after
+ * tuning. Synchronises. best_ms: host, ms per step of the chosen shape. */
+int psm_autotune(psm_ctx* ctx, int trial_steps, int* tx, int* ty, int* tz, double* best_ms);
+
+/* Enable (1) / disable (0) HIP-graph replay of 10-step sequences in psm_step. */
+int psm_set_graph(psm_ctx* ctx, int enable);
+
+/* Kernel timing: when enabled, psm_step records HIP events on the context's
+ * stream around every launch of the step kernel (eager launches only).
+ * psm_get_timing synchronises and returns the number of timed launches and
+ * their summed duration in ms; psm_reset_timing clears both. */
+int psm_set_timing(psm_ctx* ctx, int enable);
+int psm_get_timing(psm_ctx* ctx, long long* launches, double* total_ms);
+int psm_reset_timing(psm_ctx* ctx);
+
+/* Bandwidth reference (the paper's SCALE/STREAM measurement, Sec. 4): copy
+ * `bytes` (multiple of 16) from src to dst (device, 16-byte aligned, not
+ * overlapping) on hip_stream with a plain streaming copy kernel. */
+int psm_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
+
+/* Text of the last error on this thread ("" if none). Never NULL. */
+const char* psm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSM_H */

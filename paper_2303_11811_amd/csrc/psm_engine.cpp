@@ -1,0 +1,793 @@
+// psm_engine.cpp -- host side of the PSM-LBM engine: the C ABI of psm.h.
+//
+// A context owns no device memory of its own: the caller's workspace is
+// carved into per-box ping-pong PDF grids, the global particle table, the
+// per-tile candidate lists, the per-(tile, sphere) force partials and a few
+// scratch words. Particle uploads go through pinned staging. The time step
+// of Sec. 3.1 of the paper (mapping -> PSM kernel -> force reduction) is one
+// persistent fused launch plus one small reduction launch; 10-step runs can
+// be replayed from captured HIP graphs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/psm.h"
+#include "psm_internal.h"
+
+using namespace psm;
+
+// ---------------------------------------------------------------------------
+// Errors
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return fail(PSM_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+extern "C" const char* psm_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Launch shapes
+
+static const int kTX[] = {16, 32, 64, 128, 256};
+static const int kTZ[] = {1, 2, 4, 8, 16, 32};
+
+static bool shape_allowed(int tx, int ty, int tz) {
+    bool okx = false, okz = false;
+    for (int v : kTX) okx |= (v == tx);
+    for (int v : kTZ) okz |= (v == tz);
+    return okx && okz && tx * ty == WG;
+}
+
+static int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Largest number of tiles the bounding box [x-(r+1), x+(r+1)] can touch along
+// an axis of L cells cut into tiles of T cells.
+static int max_tiles_axis(double rmax, int T, int L) {
+    int E = (int)std::floor(2.0 * (rmax + 1.0)) + 2;
+    int nt = cdiv(L, T);
+    return std::min(nt, cdiv(E, T) + 1);
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout
+
+struct Layout {
+    size_t off_boxes, off_tbase, off_partbox, off_pt, off_acc, off_tcnt, off_toff, off_tpid, off_partial,
+        off_misc, off_statpart, total;
+    std::vector<size_t> off_grid[2];
+    std::vector<long long> qstride;
+    int T_max;
+    long long cap_max;
+    int P_total;
+};
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static size_t storage_bytes(int storage) { return storage == PSM_FP64 ? 8 : (storage == PSM_FP32DEV ? 4 : 2); }
+
+static int validate(const psm_box_desc* boxes, int nbox, int storage) {
+    if (!boxes || nbox <= 0) return fail(PSM_EINVAL, "need at least one box descriptor");
+    if (storage < PSM_FP64 || storage > PSM_FP16DEV) return fail(PSM_EINVAL, "unknown storage %d", storage);
+    long long P = 0;
+    for (int b = 0; b < nbox; ++b) {
+        const psm_box_desc& d = boxes[b];
+        if (d.nx < 4 || d.ny < 4 || d.nz < 4) return fail(PSM_EINVAL, "box %d: every dimension must be >= 4", b);
+        long long N = (long long)d.nx * d.ny * d.nz;
+        if (N > 0x7fffffffLL) return fail(PSM_EINVAL, "box %d: more than 2^31-1 cells", b);
+        if (!(d.tau > 0.5) || !std::isfinite(d.tau)) return fail(PSM_EINVAL, "box %d: tau must be > 1/2", b);
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(d.fext[a])) return fail(PSM_EINVAL, "box %d: non-finite body force", b);
+        if (d.max_particles < 0) return fail(PSM_EINVAL, "box %d: max_particles < 0", b);
+        if (d.mapping != PSM_MAP_LINEAR && d.mapping != PSM_MAP_SUBSAMPLE)
+            return fail(PSM_EINVAL, "box %d: unknown mapping %d", b, d.mapping);
+        if (d.mapping == PSM_MAP_SUBSAMPLE && (d.subsample_n < 1 || d.subsample_n > 16))
+            return fail(PSM_EINVAL, "box %d: subsample_n must be in 1..16", b);
+        if (d.max_particles > 0) {
+            if (!(d.max_radius >= 1.0) || !std::isfinite(d.max_radius))
+                return fail(PSM_EINVAL, "box %d: max_radius must be >= 1", b);
+            double need = 2.0 * (d.max_radius + 1.0) + 2.0;
+            if (d.nx < need || d.ny < need || d.nz < need)
+                return fail(PSM_EINVAL, "box %d: dimensions must be >= 2*(max_radius+1)+2 = %.1f", b, need);
+        }
+        P += d.max_particles;
+    }
+    if (P > 0x3fffffffLL) return fail(PSM_EINVAL, "too many particles in total");
+    return PSM_OK;
+}
+
+static Layout make_layout(const psm_box_desc* boxes, int nbox, int storage) {
+    Layout L{};
+    size_t s = storage_bytes(storage);
+    int P = 0;
+    for (int b = 0; b < nbox; ++b) P += boxes[b].max_particles;
+    L.P_total = P;
+    int Tmax = 0;
+    long long capmax = 0;
+    for (int tx : kTX)
+        for (int tz : kTZ) {
+            int ty = WG / tx;
+            long long T = 0, cap = 0;
+            for (int b = 0; b < nbox; ++b) {
+                const psm_box_desc& d = boxes[b];
+                T += (long long)cdiv(d.nx, tx) * cdiv(d.ny, ty) * cdiv(d.nz, tz);
+                if (d.max_particles > 0)
+                    cap += (long long)d.max_particles * max_tiles_axis(d.max_radius, tx, d.nx) *
+                           max_tiles_axis(d.max_radius, ty, d.ny) * max_tiles_axis(d.max_radius, tz, d.nz);
+            }
+            Tmax = (int)std::max<long long>(Tmax, T);
+            capmax = std::max(capmax, cap);
+        }
+    L.T_max = Tmax;
+    L.cap_max = std::max<long long>(capmax, 1);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    L.off_boxes = take(sizeof(BoxDev) * nbox);
+    L.off_tbase = take(sizeof(int) * (nbox + 1));
+    L.off_partbox = take(sizeof(int) * std::max(P, 1));
+    L.off_pt = take(sizeof(double) * 11 * std::max(P, 1));
+    L.off_acc = take(sizeof(double) * 6 * std::max(P, 1));
+    L.off_tcnt = take(sizeof(int) * (size_t)Tmax);
+    L.off_toff = take(sizeof(int) * ((size_t)Tmax + 1));
+    L.off_tpid = take(sizeof(int) * (size_t)L.cap_max);
+    L.off_partial = take(sizeof(double) * 6 * (size_t)L.cap_max);
+    L.off_misc = take(256);
+    L.off_statpart = take(sizeof(double) * 4 * (size_t)stats_blocks() + 64);
+    for (int p = 0; p < 2; ++p) L.off_grid[p].resize(nbox);
+    L.qstride.resize(nbox);
+    for (int b = 0; b < nbox; ++b) {
+        long long N = (long long)boxes[b].nx * boxes[b].ny * boxes[b].nz;
+        long long qs = (N + 63) / 64 * 64;   // each q array starts 512-byte aligned (FP64)
+        L.qstride[b] = qs;
+        for (int p = 0; p < 2; ++p) L.off_grid[p][b] = take(s * NQ * (size_t)qs);
+    }
+    L.total = o;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// Context
+
+struct psm_ctx {
+    int nbox = 0, storage = 0;
+    int map_mode = 0;            // 1 if any box uses sub-division sampling
+    float h_scale = 1.0f, h_inv = 1.0f;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    Layout L;
+    std::vector<psm_box_desc> desc;
+    std::vector<BoxDev> box;     // host copy of the device box table
+    std::vector<int> np;         // particles set per box
+    int P_total = 0;
+    TileShape ts{64, 4, 16};
+    int T_total = 0;
+    int grid = 0;
+    int parity = 0;
+    bool have_particles_lists = false;
+    // device pointers into the workspace
+    BoxDev* d_boxes = nullptr;
+    int* d_tbase = nullptr;
+    int* d_partbox = nullptr;
+    Particles P{};
+    int *d_tcnt = nullptr, *d_toff = nullptr, *d_tpid = nullptr;
+    double* d_partial = nullptr;
+    int* d_misc = nullptr;               // [0..1] bin stats, [8..9] dropped (u64)
+    double* d_statpart = nullptr;
+    // pinned host staging
+    double* h_stage = nullptr;
+    size_t h_stage_n = 0;
+    // graphs of 10 steps, one per starting parity
+    bool use_graph = false;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    long long timed_launches = 0;
+    double timed_ms = 0.0;
+};
+
+static const int kGraphSteps = 10;
+
+static void drop_graphs(psm_ctx* c) {
+    for (int p = 0; p < 2; ++p)
+        if (c->gexec[p]) {
+            (void)hipGraphExecDestroy(c->gexec[p]);
+            c->gexec[p] = nullptr;
+        }
+}
+
+static int upload_box_table(psm_ctx* c) {
+    std::vector<int> tb(c->nbox + 1);
+    for (int b = 0; b < c->nbox; ++b) tb[b] = c->box[b].tile_base;
+    tb[c->nbox] = c->T_total;
+    HIP_TRY(hipMemcpyAsync(c->d_boxes, c->box.data(), sizeof(BoxDev) * c->nbox, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->d_tbase, tb.data(), sizeof(int) * (c->nbox + 1), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));   // the host vectors are pageable temporaries
+    return PSM_OK;
+}
+
+static void assign_tiles(psm_ctx* c) {
+    int base = 0;
+    for (int b = 0; b < c->nbox; ++b) {
+        BoxDev& bx = c->box[b];
+        bx.ntx = cdiv(bx.nx, c->ts.tx);
+        bx.nty = cdiv(bx.ny, c->ts.ty);
+        bx.ntz = cdiv(bx.nz, c->ts.tz);
+        bx.tile_base = base;
+        base += bx.ntx * bx.nty * bx.ntz;
+    }
+    c->T_total = base;
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    int g = step_blocks_per_cu(c->storage, c->map_mode) * ncu;
+    g = std::min(g, ((c->T_total + NXCD - 1) / NXCD) * NXCD);
+    c->grid = std::max(NXCD, g / NXCD * NXCD);
+}
+
+// Rebuild the per-tile candidate lists of all boxes (synchronises).
+static int rebuild_lists(psm_ctx* c) {
+    // the step kernel must never run on half-built lists
+    c->have_particles_lists = false;
+    BinParams bp;
+    bp.boxes = c->d_boxes;
+    bp.part_box = c->d_partbox;
+    bp.P = c->P;
+    bp.tile_cnt = c->d_tcnt;
+    bp.tile_off = c->d_toff;
+    bp.tile_pid = c->d_tpid;
+    bp.P_total = c->P_total;
+    bp.T_total = c->T_total;
+    bp.ts = c->ts;
+    HIP_TRY(launch_bin(bp, c->d_misc, c->stream));
+    int stats[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(stats, c->d_misc, sizeof stats, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (stats[1] > c->L.cap_max)
+        return fail(PSM_ECAPACITY, "tile lists need %d entries, capacity %lld", stats[1], c->L.cap_max);
+    if (stats[0] > MAXC)
+        return fail(PSM_ECAPACITY, "a tile has %d sphere candidates (limit %d): use a smaller tile shape",
+                    stats[0], MAXC);
+    HIP_TRY(launch_bin_fill(bp, c->stream));
+    c->have_particles_lists = true;
+    return PSM_OK;
+}
+
+extern "C" int psm_workspace_size(const psm_box_desc* boxes, int nbox, int storage, size_t* bytes) {
+    if (!bytes) return fail(PSM_EINVAL, "bytes is NULL");
+    int rc = validate(boxes, nbox, storage);
+    if (rc) return rc;
+    *bytes = make_layout(boxes, nbox, storage).total;
+    return PSM_OK;
+}
+
+extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, double fp16_scale, void* hip_stream,
+                          void* dev_workspace, size_t workspace_bytes, psm_ctx** out) {
+    if (!out) return fail(PSM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(boxes, nbox, storage);
+    if (rc) return rc;
+    if (!dev_workspace) return fail(PSM_EINVAL, "workspace is NULL");
+    if (((uintptr_t)dev_workspace) & 255) return fail(PSM_EINVAL, "workspace must be 256-byte aligned");
+    Layout L = make_layout(boxes, nbox, storage);
+    if (workspace_bytes < L.total)
+        return fail(PSM_EINVAL, "workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+    if (storage == PSM_FP16DEV) {
+        if (fp16_scale == 0.0) fp16_scale = 1024.0;
+        int e = 0;
+        double m = std::frexp(fp16_scale, &e);
+        if (!(fp16_scale > 0.0) || m != 0.5) return fail(PSM_EINVAL, "fp16_scale must be a power of two");
+    }
+
+    psm_ctx* c = new psm_ctx();
+    c->nbox = nbox;
+    c->storage = storage;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (char*)dev_workspace;
+    c->L = L;
+    c->desc.assign(boxes, boxes + nbox);
+    for (int b = 0; b < nbox; ++b)
+        if (boxes[b].mapping == PSM_MAP_SUBSAMPLE) c->map_mode = 1;
+    if (storage == PSM_FP16DEV) {
+        c->h_scale = (float)fp16_scale;
+        c->h_inv = (float)(1.0 / fp16_scale);
+    }
+    c->P_total = L.P_total;
+    c->np.assign(nbox, 0);
+    c->box.resize(nbox);
+    int pb = 0;
+    for (int b = 0; b < nbox; ++b) {
+        const psm_box_desc& d = boxes[b];
+        BoxDev& bx = c->box[b];
+        std::memset(&bx, 0, sizeof bx);
+        bx.nx = d.nx; bx.ny = d.ny; bx.nz = d.nz;
+        bx.N = d.nx * d.ny * d.nz;
+        bx.part_base = pb;
+        bx.np = 0;
+        bx.mapping = d.mapping;
+        bx.nsub = d.mapping == PSM_MAP_SUBSAMPLE ? d.subsample_n : 1;
+        bx.qstride = L.qstride[b];
+        bx.grid[0] = c->ws + L.off_grid[0][b];
+        bx.grid[1] = c->ws + L.off_grid[1][b];
+        bx.omega = 1.0 / d.tau;
+        bx.pref = 1.0 - 1.0 / (2.0 * d.tau);
+        for (int a = 0; a < 3; ++a) bx.g[a] = d.fext[a];
+        for (int k = 0; k < 9; ++k) {
+            int q = 2 * k + 1;
+            double cg = CX[q] * d.fext[0] + CY[q] * d.fext[1] + CZ[q] * d.fext[2];
+            bx.fa[k] = 3.0 * bx.pref * wq(q) * cg;
+            bx.fs[k] = 9.0 * bx.pref * wq(q) * cg;
+        }
+        int dims[3] = {d.nx, d.ny, d.nz};
+        for (int a = 0; a < 3; ++a) {
+            bx.L[a] = dims[a];
+            bx.halfL[a] = 0.5 * dims[a];
+        }
+        for (int k = 0; k < 16; ++k) bx.sub_off[k] = k < bx.nsub ? (k + 0.5) / bx.nsub - 0.5 : 0.0;
+        bx.reach = 0.8660254037844386 * (1.0 - 1.0 / bx.nsub) + 1e-9;
+        bx.pw[0] = bx.pref * W0;
+        bx.pw[1] = bx.pref * W1;
+        bx.pw[2] = bx.pref * W2;
+        pb += d.max_particles;
+    }
+    c->d_boxes = (BoxDev*)(c->ws + L.off_boxes);
+    c->d_tbase = (int*)(c->ws + L.off_tbase);
+    c->d_partbox = (int*)(c->ws + L.off_partbox);
+    double* pt = (double*)(c->ws + L.off_pt);
+    size_t P1 = std::max(c->P_total, 1);
+    double** fields[11] = {&c->P.x, &c->P.y, &c->P.z, &c->P.r, &c->P.fr, &c->P.ux,
+                           &c->P.uy, &c->P.uz, &c->P.ox, &c->P.oy, &c->P.oz};
+    for (int k = 0; k < 11; ++k) *fields[k] = pt + k * P1;
+    c->P.acc = (double*)(c->ws + L.off_acc);
+    c->d_tcnt = (int*)(c->ws + L.off_tcnt);
+    c->d_toff = (int*)(c->ws + L.off_toff);
+    c->d_tpid = (int*)(c->ws + L.off_tpid);
+    c->d_partial = (double*)(c->ws + L.off_partial);
+    c->d_misc = (int*)(c->ws + L.off_misc);
+    c->d_statpart = (double*)(c->ws + L.off_statpart);
+
+    int err = PSM_OK;
+    auto hip_ok = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && err == PSM_OK) err = fail(PSM_EHIP, "%s: %s", what, hipGetErrorString(e));
+    };
+    c->h_stage_n = std::max<size_t>(11 * P1 + 64, 6 * P1 + 64);
+    hip_ok(hipHostMalloc((void**)&c->h_stage, sizeof(double) * c->h_stage_n, hipHostMallocDefault), "hipHostMalloc");
+    if (err) { delete c; return err; }
+
+    std::vector<int> partbox(P1, 0);
+    for (int b = 0; b < nbox; ++b)
+        for (int p = 0; p < boxes[b].max_particles; ++p) partbox[c->box[b].part_base + p] = b;
+    hip_ok(hipMemcpyAsync(c->d_partbox, partbox.data(), sizeof(int) * P1, hipMemcpyHostToDevice, c->stream),
+           "upload part_box");
+    hip_ok(hipMemsetAsync(c->P.acc, 0, sizeof(double) * 6 * P1, c->stream), "clear forces");
+    hip_ok(hipMemsetAsync(pt, 0, sizeof(double) * 11 * P1, c->stream), "clear particles");
+    hip_ok(hipStreamSynchronize(c->stream), "sync");
+    if (err) { (void)hipHostFree(c->h_stage); delete c; return err; }
+
+    assign_tiles(c);
+    int r2 = upload_box_table(c);
+    if (r2 == PSM_OK) r2 = rebuild_lists(c);
+    if (r2 != PSM_OK) {
+        (void)hipHostFree(c->h_stage);
+        delete c;
+        return r2;
+    }
+    *out = c;
+    return PSM_OK;
+}
+
+extern "C" int psm_destroy(psm_ctx* c) {
+    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    delete c;
+    return PSM_OK;
+}
+
+static int check_box(psm_ctx* c, int box) {
+    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    if (box < 0 || box >= c->nbox) return fail(PSM_EINVAL, "box %d out of range [0,%d)", box, c->nbox);
+    return PSM_OK;
+}
+
+extern "C" int psm_set_equilibrium(psm_ctx* c, int box, const double* rho, const double* u) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    if (!u) return fail(PSM_EINVAL, "u is NULL");
+    HIP_TRY(launch_set_equilibrium(c->storage, c->box[box], c->parity, rho, u, c->h_scale, c->stream));
+    return PSM_OK;
+}
+
+extern "C" int psm_set_pdfs(psm_ctx* c, int box, const double* f) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    if (!f) return fail(PSM_EINVAL, "f is NULL");
+    HIP_TRY(launch_set_pdfs(c->storage, c->box[box], c->parity, f, c->h_scale, c->stream));
+    return PSM_OK;
+}
+
+extern "C" int psm_get_pdfs(psm_ctx* c, int box, double* f) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    if (!f) return fail(PSM_EINVAL, "f is NULL");
+    HIP_TRY(launch_get_pdfs(c->storage, c->box[box], c->parity, f, c->h_inv, c->stream));
+    return PSM_OK;
+}
+
+extern "C" int psm_get_pdfs_at(psm_ctx* c, int box, int ncells, const int* cells, double* out) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    if (ncells < 0) return fail(PSM_EINVAL, "ncells < 0");
+    if (ncells == 0) return PSM_OK;
+    if (!cells || !out) return fail(PSM_EINVAL, "cells/out is NULL");
+    HIP_TRY(launch_get_pdfs_at(c->storage, c->box[box], c->parity, cells, ncells, out, c->h_inv, c->stream));
+    return PSM_OK;
+}
+
+extern "C" int psm_get_macroscopic(psm_ctx* c, int box, double* rho, double* u) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    if (!rho || !u) return fail(PSM_EINVAL, "rho/u is NULL");
+    HIP_TRY(launch_macroscopic(c->storage, c->box[box], c->parity, rho, u, c->h_inv, c->stream));
+    return PSM_OK;
+}
+
+// f(r) = V_a - r + 1/2 of eq. (26), with V_a the closed form of eq. (27):
+// the integral of sqrt(r^2 - x^2 - y^2) over the unit square.
+static double solid_fraction_offset(double r) {
+    double r2 = r * r;
+    double s = std::sqrt(r2 - 0.5);
+    double Va = (1.0 / 12.0 - r2) * std::atan((0.5 * s) / (0.5 - r2)) + s / 3.0 +
+                (r2 - 1.0 / 12.0) * std::atan(0.5 / s) - (4.0 / 3.0) * r * r2 * std::atan(0.25 / (r * s));
+    return Va - r + 0.5;
+}
+
+static double wrap_coord(double v, double L) {
+    double w = v - L * std::floor(v / L);
+    if (w >= L) w -= L;   // v slightly below a multiple of L
+    if (w < 0.0) w = 0.0;
+    return w;
+}
+
+extern "C" int psm_set_particles(psm_ctx* c, int box, int n, const double* x, const double* r, const double* U,
+                                 const double* omega) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    const psm_box_desc& d = c->desc[box];
+    if (n < 0) return fail(PSM_EINVAL, "n < 0");
+    if (n > d.max_particles) return fail(PSM_ECAPACITY, "box %d holds at most %d particles (got %d)", box, d.max_particles, n);
+    if (n > 0 && (!x || !r || !U)) return fail(PSM_EINVAL, "x/r/U is NULL");
+    for (int p = 0; p < n; ++p) {
+        if (!(r[p] >= 1.0 && r[p] <= d.max_radius))
+            return fail(PSM_EINVAL, "particle %d: radius %g outside [1, %g]", p, r[p], d.max_radius);
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(x[3 * p + a]) || !std::isfinite(U[3 * p + a]) ||
+                (omega && !std::isfinite(omega[3 * p + a])))
+                return fail(PSM_EINVAL, "particle %d: non-finite input", p);
+        }
+    }
+    // staging: 11 SoA columns of length n, in the order of the device table
+    int m = d.max_particles;
+    double* st = c->h_stage;
+    double Lx = d.nx, Ly = d.ny, Lz = d.nz;
+    for (int p = 0; p < n; ++p) {
+        st[0 * m + p] = wrap_coord(x[3 * p + 0], Lx);
+        st[1 * m + p] = wrap_coord(x[3 * p + 1], Ly);
+        st[2 * m + p] = wrap_coord(x[3 * p + 2], Lz);
+        st[3 * m + p] = r[p];
+        st[4 * m + p] = solid_fraction_offset(r[p]);
+        for (int a = 0; a < 3; ++a) {
+            st[(5 + a) * m + p] = U[3 * p + a];
+            st[(8 + a) * m + p] = omega ? omega[3 * p + a] : 0.0;
+        }
+    }
+    double* cols[11] = {c->P.x, c->P.y, c->P.z, c->P.r, c->P.fr, c->P.ux, c->P.uy, c->P.uz, c->P.ox, c->P.oy, c->P.oz};
+    int pb = c->box[box].part_base;
+    if (n > 0)
+        for (int k = 0; k < 11; ++k)
+            HIP_TRY(hipMemcpyAsync(cols[k] + pb, st + (size_t)k * m, sizeof(double) * n, hipMemcpyHostToDevice,
+                                   c->stream));
+    c->box[box].np = n;
+    c->np[box] = n;
+    HIP_TRY(hipMemcpyAsync(&c->d_boxes[box].np, &c->box[box].np, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));   // staging is reused by the next call
+    return rebuild_lists(c);
+}
+
+static int step_params(psm_ctx* c, int parity, StepParams& kp) {
+    kp.boxes = c->d_boxes;
+    kp.box_tile_base = c->d_tbase;
+    kp.nbox = c->nbox;
+    kp.P = c->P;
+    kp.tile_off = c->d_toff;
+    kp.tile_pid = c->d_tpid;
+    kp.partial = c->d_partial;
+    kp.T_total = c->T_total;
+    kp.tx = c->ts.tx; kp.ty = c->ts.ty; kp.tz = c->ts.tz;
+    kp.parity = parity;
+    kp.h_scale = c->h_scale;
+    kp.h_inv = c->h_inv;
+    return PSM_OK;
+}
+
+static ReduceParams reduce_params(psm_ctx* c) {
+    ReduceParams rp;
+    rp.boxes = c->d_boxes;
+    rp.nbox = c->nbox;
+    rp.part_box = c->d_partbox;
+    rp.P = c->P;
+    rp.tile_off = c->d_toff;
+    rp.tile_pid = c->d_tpid;
+    rp.partial = c->d_partial;
+    rp.P_total = c->P_total;
+    rp.ts = c->ts;
+    return rp;
+}
+
+static hipEvent_t next_event(psm_ctx* c) {
+    if (c->ev_used == c->ev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev.push_back(e);
+    }
+    return c->ev[c->ev_used++];
+}
+
+static int enqueue_step(psm_ctx* c, bool timed) {
+    StepParams kp;
+    step_params(c, c->parity, kp);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        e0 = next_event(c);
+        e1 = next_event(c);
+        if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
+    }
+    HIP_TRY(launch_step(c->storage, c->map_mode, kp, c->grid, c->stream));
+    if (timed && e1) HIP_TRY(hipEventRecord(e1, c->stream));
+    HIP_TRY(launch_reduce(reduce_params(c), c->stream));
+    c->parity ^= 1;
+    return PSM_OK;
+}
+
+static int build_graph(psm_ctx* c, int start_parity) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int saved = c->parity;
+    c->parity = start_parity;
+    int rc = PSM_OK;
+    for (int s = 0; s < kGraphSteps && rc == PSM_OK; ++s) rc = enqueue_step(c, false);
+    c->parity = saved;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (rc != PSM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(PSM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->gexec[start_parity], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(PSM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    return PSM_OK;
+}
+
+extern "C" int psm_step(psm_ctx* c, int nsteps) {
+    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(PSM_EINVAL, "nsteps < 0");
+    if (!c->have_particles_lists) return fail(PSM_ESTATE, "tile lists are not built");
+    int left = nsteps;
+    if (c->use_graph && !c->timing) {
+        while (left >= kGraphSteps) {
+            int p = c->parity;
+            if (!c->gexec[p]) {
+                int rc = build_graph(c, p);
+                if (rc) return rc;
+            }
+            HIP_TRY(hipGraphLaunch(c->gexec[p], c->stream));
+            left -= kGraphSteps;   // an even count: the parity is unchanged
+        }
+    }
+    for (; left > 0; --left) {
+        int rc = enqueue_step(c, c->timing);
+        if (rc) return rc;
+    }
+    return PSM_OK;
+}
+
+extern "C" int psm_get_forces(psm_ctx* c, int box, double* F, double* T) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    int n = c->np[box];
+    if (n == 0) return PSM_OK;
+    if (!F || !T) return fail(PSM_EINVAL, "F/T is NULL");
+    double* st = c->h_stage;
+    HIP_TRY(hipMemcpyAsync(st, c->P.acc + 6LL * c->box[box].part_base, sizeof(double) * 6 * n,
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int p = 0; p < n; ++p)
+        for (int a = 0; a < 3; ++a) {
+            F[3 * p + a] = st[6 * p + a];
+            T[3 * p + a] = st[6 * p + 3 + a];
+        }
+    return PSM_OK;
+}
+
+extern "C" int psm_get_solid_fraction(psm_ctx* c, int box, double* B, int* pid) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    if (!B || !pid) return fail(PSM_EINVAL, "B/pid is NULL");
+    unsigned long long* dropped = (unsigned long long*)(c->d_misc + 8);
+    HIP_TRY(hipMemsetAsync(dropped, 0, sizeof(unsigned long long), c->stream));
+    HIP_TRY(launch_map_dense(c->box[box], c->P, c->d_toff, c->d_tpid, c->ts, B, pid, dropped, c->stream));
+    return PSM_OK;
+}
+
+extern "C" int psm_get_stats(psm_ctx* c, int box, double* mass, double* momentum, long long* slot_overflows) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    double* out = c->d_statpart + 4 * stats_blocks();
+    HIP_TRY(launch_stats(c->storage, c->box[box], c->parity, c->h_inv, c->d_statpart, out, c->stream));
+    unsigned long long* dropped = (unsigned long long*)(c->d_misc + 8);
+    HIP_TRY(hipMemsetAsync(dropped, 0, sizeof(unsigned long long), c->stream));
+    HIP_TRY(launch_map_dense(c->box[box], c->P, c->d_toff, c->d_tpid, c->ts, nullptr, nullptr, dropped, c->stream));
+    double* st = c->h_stage;
+    HIP_TRY(hipMemcpyAsync(st, out, sizeof(double) * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(st + 4, dropped, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (mass) *mass = st[0];
+    if (momentum)
+        for (int a = 0; a < 3; ++a) momentum[a] = st[1 + a];
+    unsigned long long dr;
+    std::memcpy(&dr, st + 4, sizeof dr);
+    if (slot_overflows) *slot_overflows = (long long)dr;
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(st[k])) return fail(PSM_ENONFINITE, "box %d: non-finite mass or momentum", box);
+    return PSM_OK;
+}
+
+extern "C" int psm_set_launch(psm_ctx* c, int tx, int ty, int tz) {
+    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    if (!shape_allowed(tx, ty, tz)) return fail(PSM_EINVAL, "launch shape %dx%dx%d not allowed", tx, ty, tz);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    TileShape old = c->ts;
+    c->ts = TileShape{tx, ty, tz};
+    assign_tiles(c);
+    int rc = upload_box_table(c);
+    if (rc == PSM_OK) rc = rebuild_lists(c);
+    if (rc != PSM_OK) {
+        std::string msg = g_err;
+        c->ts = old;
+        assign_tiles(c);
+        if (upload_box_table(c) == PSM_OK) rebuild_lists(c);
+        g_err = msg;
+        return rc;
+    }
+    drop_graphs(c);
+    return PSM_OK;
+}
+
+extern "C" int psm_get_launch(psm_ctx* c, int* tx, int* ty, int* tz) {
+    if (!c || !tx || !ty || !tz) return fail(PSM_EINVAL, "NULL argument");
+    *tx = c->ts.tx; *ty = c->ts.ty; *tz = c->ts.tz;
+    return PSM_OK;
+}
+
+extern "C" int psm_set_graph(psm_ctx* c, int enable) {
+    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    c->use_graph = enable != 0;
+    if (!c->use_graph) drop_graphs(c);
+    return PSM_OK;
+}
+
+extern "C" int psm_set_timing(psm_ctx* c, int enable) {
+    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    c->timing = enable != 0;
+    return PSM_OK;
+}
+
+extern "C" int psm_get_timing(psm_ctx* c, long long* launches, double* total_ms) {
+    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+        c->timed_ms += ms;
+        c->timed_launches++;
+    }
+    c->ev_used = 0;
+    if (launches) *launches = c->timed_launches;
+    if (total_ms) *total_ms = c->timed_ms;
+    return PSM_OK;
+}
+
+extern "C" int psm_reset_timing(psm_ctx* c) {
+    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->ev_used = 0;
+    c->timed_launches = 0;
+    c->timed_ms = 0.0;
+    return PSM_OK;
+}
+
+extern "C" int psm_autotune(psm_ctx* c, int trial_steps, int* tx, int* ty, int* tz, double* best_ms) {
+    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    if (trial_steps < 1) return fail(PSM_EINVAL, "trial_steps must be >= 1");
+    TileShape best = c->ts;
+    double best_t = 1e300;
+    bool was_timing = c->timing, was_graph = c->use_graph;
+    c->timing = false;
+    c->use_graph = false;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int maxdim = 0;
+    for (auto& d : c->desc) maxdim = std::max(maxdim, d.nx);
+    for (int txv : kTX) {
+        // tiles much wider than the widest box only idle lanes
+        if (txv > 2 * std::max(maxdim, 16)) continue;
+        for (int tzv : kTZ) {
+            int tyv = WG / txv;
+            if (psm_set_launch(c, txv, tyv, tzv) != PSM_OK) continue;
+            int rc = psm_step(c, 2);
+            if (rc) break;
+            (void)hipEventRecord(e0, c->stream);
+            rc = psm_step(c, trial_steps);
+            if (rc) break;
+            (void)hipEventRecord(e1, c->stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            double per = ms / trial_steps;
+            if (per < best_t) {
+                best_t = per;
+                best = c->ts;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->timing = was_timing;
+    c->use_graph = was_graph;
+    int rc = psm_set_launch(c, best.tx, best.ty, best.tz);
+    if (rc) return rc;
+    if (tx) *tx = best.tx;
+    if (ty) *ty = best.ty;
+    if (tz) *tz = best.tz;
+    if (best_ms) *best_ms = best_t;
+    return PSM_OK;
+}
+
+extern "C" int psm_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream) {
+    if (!src || !dst) return fail(PSM_EINVAL, "NULL pointer");
+    if (bytes % 16) return fail(PSM_EINVAL, "bytes must be a multiple of 16");
+    if (((uintptr_t)src | (uintptr_t)dst) & 15) return fail(PSM_EINVAL, "pointers must be 16-byte aligned");
+    const char* s = (const char*)src;
+    char* d = (char*)dst;
+    if (s < d + bytes && d < s + bytes) return fail(PSM_EINVAL, "buffers overlap");
+    HIP_TRY(launch_stream_copy(src, dst, bytes, (hipStream_t)hip_stream));
+    return PSM_OK;
+}

@@ -1,0 +1,841 @@
+// psm_kernels.hip -- gfx950 kernels of the PSM-LBM hot path.
+//
+// Method: Kemmler et al., arXiv 2303.11811.
+//   Sec. 2.1   D3Q19 SRT collision with forcing, eqs. (1)-(8)
+//   Sec. 2.3   PSM collision, solid operator, particle velocity at the cell
+//              centre, hydrodynamic force and torque, eqs. (17)-(22)
+//   Sec. 2.3.2 linear-approximation solid fraction, eqs. (25)-(27)
+//   Sec. 3.1   GPU time step: mapping -> PSM kernel -> force reduction
+//
+// Storage is pull-scheme: grid[p] holds the post-collision PDFs of the last
+// step at their source cell, so a cell gathers f_q(x,t) = grid[p][q][x - c_q]
+// (eq. 2 read backwards), collides, and writes grid[p^1][q][x] aligned.
+// The paper's separate mapping / setU / redF kernels are fused into the
+// stream-collide launch: each workgroup stages its tile's sphere candidates in
+// LDS, maps solid fractions in registers, evaluates U_p(x) (eq. 20) on the fly
+// and sums the per-sphere force/torque of its tile deterministically.
+#include "psm_internal.h"
+
+namespace psm {
+
+#define GLOBAL __attribute__((address_space(1)))
+typedef const GLOBAL char GCHAR;
+
+// ---------------------------------------------------------------------------
+// Storage traits: FP64 stores f; the deviation forms store d = f - w_q
+// (FP16 as scale * d) and compute in FP32.
+struct St64 {
+    using T = double;
+    using R = double;
+    static constexpr bool DEV = false;
+    __device__ static R loadb(const GCHAR* b, unsigned off, float) { return *(const GLOBAL T*)(b + off); }
+    __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float) { *(GLOBAL T*)(b + off) = v; }
+    __device__ static double to_f64(T v, float) { return v; }
+    __device__ static T from_f64(double v, float) { return v; }
+};
+struct St32 {
+    using T = float;
+    using R = float;
+    static constexpr bool DEV = true;
+    __device__ static R loadb(const GCHAR* b, unsigned off, float) { return *(const GLOBAL T*)(b + off); }
+    __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float) { *(GLOBAL T*)(b + off) = v; }
+    __device__ static double to_f64(T v, float) { return (double)v; }
+    __device__ static T from_f64(double v, float) { return (float)v; }
+};
+struct St16 {
+    using T = _Float16;
+    using R = float;
+    static constexpr bool DEV = true;
+    // scale is a power of two: multiplication by it and by 1/scale is exact
+    __device__ static R loadb(const GCHAR* b, unsigned off, float inv) { return (float)*(const GLOBAL T*)(b + off) * inv; }
+    __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float scale) {
+        *(GLOBAL T*)(b + off) = (_Float16)(v * scale);
+    }
+    __device__ static double to_f64(T v, float inv) { return (double)((float)v * inv); }
+    __device__ static T from_f64(double v, float scale) { return (_Float16)(float)(v * (double)scale); }
+};
+
+__device__ inline int find_box(const int* tile_base, int nbox, int t) {
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (tile_base[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Uniform (wave-invariant) data is read through the constant address space so
+// that it lands in scalar registers.
+#define PSM_CONST __attribute__((address_space(4)))
+template <class T> __device__ __forceinline__ const PSM_CONST T* cptr(const T* p) {
+    return (const PSM_CONST T*)p;
+}
+
+// One inverse pair (q, q+1) of the plain SRT update with forcing:
+//   E_q(U) = w (rho + 3 c.U + 4.5 (c.U)^2 - 1.5 U.U) = s + a, E_qbar(U) = s - a  (eq. 5)
+//   t_q = (E_q(U) - f_q)/tau + F_q      (eq. 3; eq. 8 with the Guo prefactor)
+//   f~_q = f_q + t_q
+// rho is the density deviation for the deviation storage forms.
+template <class R, int Q>
+__device__ __forceinline__ void pair_fluid(R& fq, R& fb, R base, R Ux, R Uy, R Uz, R fa, R fs, R pwUg3,
+                                           R omega) {
+    constexpr R w = (R)wq(Q);
+    constexpr R cx = (R)CX[Q], cy = (R)CY[Q], cz = (R)CZ[Q];
+    R cu = cx * Ux + cy * Uy + cz * Uz;
+    R sU = w * base + ((R)4.5 * w) * (cu * cu);
+    R aU = ((R)3.0 * w) * cu;
+    R Fs = fs * cu - pwUg3;
+    fq = fq + (omega * (sU + aU - fq) + (Fs + fa));
+    fb = fb + (omega * (sU - aU - fb) + (Fs - fa));
+}
+
+// The same pair under PSM (eqs. 17-19):
+//   f~_q = f_q + (1-B) t_q + B (f_qbar - E_qbar(U) - f_q) + sum_s B_s E_q(U_p,s)
+// with the slot sum folded into ten cell scalars:
+//   sum_s B_s E_q(V_s) = w (A0 + 4.5 c.M.c) + 3 w c.P,
+//   A0 = sum_s B_s (rho - 1.5 V_s.V_s), M = sum_s B_s V_s V_s^T, P = sum_s B_s V_s.
+template <class R, int Q>
+__device__ __forceinline__ void pair_psm(R& fq, R& fb, R base, R Ux, R Uy, R Uz, R fa, R fs, R pwUg3, R omega,
+                                         R Bt, R omB, R A0, R Mxx, R Myy, R Mzz, R Mxy, R Mxz, R Myz, R Px,
+                                         R Py, R Pz) {
+    constexpr R w = (R)wq(Q);
+    constexpr int ix = CX[Q], iy = CY[Q], iz = CZ[Q];
+    constexpr R cx = (R)ix, cy = (R)iy, cz = (R)iz;
+    R cu = cx * Ux + cy * Uy + cz * Uz;
+    R sU = w * base + ((R)4.5 * w) * (cu * cu);
+    R aU = ((R)3.0 * w) * cu;
+    R Fs = fs * cu - pwUg3;
+    R tq = omega * (sU + aU - fq) + (Fs + fa);
+    R tb = omega * (sU - aU - fb) + (Fs - fa);
+    R cMc = (R)(ix * ix) * Mxx + (R)(iy * iy) * Myy + (R)(iz * iz) * Mzz +
+            (R)(2 * ix * iy) * Mxy + (R)(2 * ix * iz) * Mxz + (R)(2 * iy * iz) * Myz;
+    R cP = cx * Px + cy * Py + cz * Pz;
+    R sV = w * A0 + ((R)4.5 * w) * cMc;
+    R aV = ((R)3.0 * w) * cP;
+    R Sq = Bt * (fb - (sU - aU) - fq) + (sV + aV);
+    R Sb = Bt * (fq - (sU + aU) - fb) + (sV - aV);
+    R nq = (fq + omB * tq) + Sq;
+    R nb = (fb + omB * tb) + Sb;
+    fq = nq;
+    fb = nb;
+}
+
+// Particle velocity at the cell centre, eq. (20): U_p + Omega x d.
+__device__ __forceinline__ void particle_velocity(int c, double dx, double dy, double dz, const double* ux,
+                                                  const double* uy, const double* uz, const double* ox,
+                                                  const double* oy, const double* oz, double& vx, double& vy,
+                                                  double& vz) {
+    vx = ux[c] + (oy[c] * dz - oz[c] * dy);
+    vy = uy[c] + (oz[c] * dx - ox[c] * dz);
+    vz = uz[c] + (ox[c] * dy - oy[c] * dx);
+}
+
+template <class S, int MAP>
+__global__ __launch_bounds__(WG) void k_psm_step(StepParams kp) {
+    using R = typename S::R;
+    using T = typename S::T;
+
+    __shared__ double s_px[MAXC], s_py[MAXC], s_pz[MAXC], s_pr[MAXC], s_pfr[MAXC];
+    __shared__ double s_ux[MAXC], s_uy[MAXC], s_uz[MAXC], s_ox[MAXC], s_oy[MAXC], s_oz[MAXC];
+    __shared__ int s_pid[MAXC];
+    __shared__ double s_acc[NWAVE][6][MAXC];
+
+    const int tid = threadIdx.x;
+    const int TX = kp.tx, TY = kp.ty, TZ = kp.tz;
+    const int lx = tid % TX, ly = tid / TX;
+    const int wave = tid >> 6, lane = tid & 63;
+
+    // XCD-aware persistent schedule: workgroup b runs on die b % 8; each die
+    // walks one contiguous eighth of the tile list so that x-neighbouring
+    // tiles (which share the cache lines of the shifted pulls) meet in the
+    // same L2.
+    const int G = gridDim.x;
+    const int xcd = blockIdx.x % NXCD;
+    const int gx8 = (G - xcd + NXCD - 1) / NXCD;
+    const int m = blockIdx.x / NXCD;
+    const int t_begin = (int)(((long long)kp.T_total * xcd) / NXCD);
+    const int t_end = (int)(((long long)kp.T_total * (xcd + 1)) / NXCD);
+
+    const PSM_CONST BoxDev* boxes = cptr(kp.boxes);
+    const PSM_CONST int* tile_off = cptr(kp.tile_off);
+
+    for (int t = t_begin + m; t < t_end; t += gx8) {
+        int b = 0;
+        if (kp.nbox > 1) {
+            const PSM_CONST int* tb = cptr(kp.box_tile_base);
+            int lo = 0, hi = kp.nbox - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (tb[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            b = lo;
+        }
+        const PSM_CONST BoxDev& bx = boxes[b];
+        const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
+        const int ntx = bx.ntx, nty = bx.nty;
+        const int lt = t - bx.tile_base;
+        const int tcx = lt % ntx;
+        const int tcy = (lt / ntx) % nty;
+        const int tcz = lt / (ntx * nty);
+        const int e0 = tile_off[t];
+        const int nc = tile_off[t + 1] - e0;
+
+        if (nc > 0) {
+            for (int c = tid; c < nc; c += WG) {
+                int p = kp.tile_pid[e0 + c];
+                s_pid[c] = p;
+                s_px[c] = kp.P.x[p]; s_py[c] = kp.P.y[p]; s_pz[c] = kp.P.z[p];
+                s_pr[c] = kp.P.r[p]; s_pfr[c] = kp.P.fr[p];
+                s_ux[c] = kp.P.ux[p]; s_uy[c] = kp.P.uy[p]; s_uz[c] = kp.P.uz[p];
+                s_ox[c] = kp.P.ox[p]; s_oy[c] = kp.P.oy[p]; s_oz[c] = kp.P.oz[p];
+            }
+            for (int i = tid; i < NWAVE * 6 * MAXC; i += WG) (&s_acc[0][0][0])[i] = 0.0;
+        }
+        __syncthreads();
+
+        const int x = tcx * TX + lx;
+        const int y = tcy * TY + ly;
+        const bool lane_ok = (x < nx) && (y < ny);
+        const int xs = lane_ok ? x : 0, ys = lane_ok ? y : 0;
+        const int xm = xs == 0 ? nx - 1 : xs - 1, xp = xs == nx - 1 ? 0 : xs + 1;
+        const int ym = ys == 0 ? ny - 1 : ys - 1, yp = ys == ny - 1 ? 0 : ys + 1;
+        const long long qs = bx.qstride;
+        const T* __restrict__ src = (const T*)bx.grid[kp.parity];
+        T* __restrict__ dst = (T*)bx.grid[kp.parity ^ 1];
+        const R omega = (R)bx.omega;
+        const R gx = (R)bx.g[0], gy = (R)bx.g[1], gz = (R)bx.g[2];
+        const double Lx = bx.L[0], Ly = bx.L[1], Lz = bx.L[2];
+        const double hLx = bx.halfL[0], hLy = bx.halfL[1], hLz = bx.halfL[2];
+        const double cxc = xs + 0.5, cyc = ys + 0.5;
+
+        for (int k = 0; k < TZ; ++k) {
+            const int z = tcz * TZ + k;
+            if (z >= nz) break;
+            const double czc = z + 0.5;
+            // Per-q grid bases stay scalar: laundering them through an empty asm
+            // keeps the compiler from hoisting 2 x 19 64-bit addresses out of
+            // the loop into vector registers. Offsets are 32-bit bytes.
+            long long qsb = qs * (long long)sizeof(T);
+            const GCHAR* sb = (const GCHAR*)src;
+            GLOBAL char* db = (GLOBAL char*)dst;
+            asm volatile("" : "+s"(qsb), "+s"(sb), "+s"(db));
+
+            // 1. solid fractions of this cell from the staged candidates (Sec. 2.3.2)
+            int c0 = -1, c1 = -1;
+            double B0 = 0.0, B1 = 0.0;
+            if (nc > 0) {
+                Slots sl;
+                slots_init(sl);
+                if (lane_ok) {
+                    for (int c = 0; c < nc; ++c) {
+                        double dx = min_image(cxc - s_px[c], Lx, hLx);
+                        double dy = min_image(cyc - s_py[c], Ly, hLy);
+                        double dz = min_image(czc - s_pz[c], Lz, hLz);
+                        double B = MAP == 0 ? overlap_linear(dx, dy, dz, s_pr[c], s_pfr[c])
+                                            : overlap_subsample(dx, dy, dz, s_pr[c], bx.nsub, bx.sub_off, bx.reach);
+                        if (B > 0.0) slots_insert(sl, c, s_pid[c], B);
+                    }
+                    slots_finish(sl);
+                }
+                c0 = sl.c0; c1 = sl.c1; B0 = sl.B0; B1 = sl.B1;
+            }
+            const bool psm_wave = __ballot(c0 >= 0) != 0ull;
+
+            // 2. pull: f_q(x) = grid[q][x - c_q]
+            const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+            const int r00 = nx * (ys + ny * z);
+            const int rm0 = nx * (ym + ny * z), rp0 = nx * (yp + ny * z);
+            const int r0m = nx * (ys + ny * zm), r0p = nx * (ys + ny * zp);
+            const int rmm = nx * (ym + ny * zm), rpp = nx * (yp + ny * zp);
+            const int rmp = nx * (ym + ny * zp), rpm = nx * (yp + ny * zm);
+            R hx = 0, hy = 0, hz = 0;   // 2 j - U, for the force of eq. (21)
+            if (lane_ok) {
+                R f[NQ];
+                f[0] = S::loadb(sb + 0 * qsb, (unsigned)(xs + r00) * (unsigned)sizeof(T), kp.h_inv);
+                f[1] = S::loadb(sb + 1 * qsb, (unsigned)(xm + r00) * (unsigned)sizeof(T), kp.h_inv);
+                f[2] = S::loadb(sb + 2 * qsb, (unsigned)(xp + r00) * (unsigned)sizeof(T), kp.h_inv);
+                f[3] = S::loadb(sb + 3 * qsb, (unsigned)(xs + rm0) * (unsigned)sizeof(T), kp.h_inv);
+                f[4] = S::loadb(sb + 4 * qsb, (unsigned)(xs + rp0) * (unsigned)sizeof(T), kp.h_inv);
+                f[5] = S::loadb(sb + 5 * qsb, (unsigned)(xs + r0m) * (unsigned)sizeof(T), kp.h_inv);
+                f[6] = S::loadb(sb + 6 * qsb, (unsigned)(xs + r0p) * (unsigned)sizeof(T), kp.h_inv);
+                f[7] = S::loadb(sb + 7 * qsb, (unsigned)(xm + rm0) * (unsigned)sizeof(T), kp.h_inv);
+                f[8] = S::loadb(sb + 8 * qsb, (unsigned)(xp + rp0) * (unsigned)sizeof(T), kp.h_inv);
+                f[9] = S::loadb(sb + 9 * qsb, (unsigned)(xm + rp0) * (unsigned)sizeof(T), kp.h_inv);
+                f[10] = S::loadb(sb + 10 * qsb, (unsigned)(xp + rm0) * (unsigned)sizeof(T), kp.h_inv);
+                f[11] = S::loadb(sb + 11 * qsb, (unsigned)(xm + r0m) * (unsigned)sizeof(T), kp.h_inv);
+                f[12] = S::loadb(sb + 12 * qsb, (unsigned)(xp + r0p) * (unsigned)sizeof(T), kp.h_inv);
+                f[13] = S::loadb(sb + 13 * qsb, (unsigned)(xm + r0p) * (unsigned)sizeof(T), kp.h_inv);
+                f[14] = S::loadb(sb + 14 * qsb, (unsigned)(xp + r0m) * (unsigned)sizeof(T), kp.h_inv);
+                f[15] = S::loadb(sb + 15 * qsb, (unsigned)(xs + rmm) * (unsigned)sizeof(T), kp.h_inv);
+                f[16] = S::loadb(sb + 16 * qsb, (unsigned)(xs + rpp) * (unsigned)sizeof(T), kp.h_inv);
+                f[17] = S::loadb(sb + 17 * qsb, (unsigned)(xs + rmp) * (unsigned)sizeof(T), kp.h_inv);
+                f[18] = S::loadb(sb + 18 * qsb, (unsigned)(xs + rpm) * (unsigned)sizeof(T), kp.h_inv);
+
+                // 3. moments, eqs. (6)-(7); U carries the f/2 shift
+                R rho = ((((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) +
+                         (((f[8] + f[9]) + (f[10] + f[11])) + ((f[12] + f[13]) + (f[14] + f[15])))) +
+                        ((f[16] + f[17]) + f[18]);
+                R jx = ((f[1] - f[2]) + (f[7] - f[8])) + ((f[9] - f[10]) + (f[11] - f[12])) + (f[13] - f[14]);
+                R jy = ((f[3] - f[4]) + (f[7] - f[8])) + ((f[10] - f[9]) + (f[15] - f[16])) + (f[17] - f[18]);
+                R jz = ((f[5] - f[6]) + (f[11] - f[12])) + ((f[14] - f[13]) + (f[15] - f[16])) + (f[18] - f[17]);
+                const R half = (R)0.5;
+                R Ux = jx + half * gx, Uy = jy + half * gy, Uz = jz + half * gz;
+                R uu = Ux * Ux + Uy * Uy + Uz * Uz;
+                R base = rho - (R)1.5 * uu;
+                R Ug3 = (R)3.0 * (Ux * gx + Uy * gy + Uz * gz);
+                const R pu0 = (R)bx.pw[0] * Ug3, pu1 = (R)bx.pw[1] * Ug3, pu2 = (R)bx.pw[2] * Ug3;
+
+                // 4. collision
+                if (!psm_wave) {
+                    f[0] = f[0] + (omega * ((R)W0 * base - f[0]) - pu0);
+#define PSM_PAIR(Q)                                                                                           \
+    pair_fluid<R, Q>(f[Q], f[Q + 1], base, Ux, Uy, Uz, (R)bx.fa[Q / 2], (R)bx.fs[Q / 2], Q < 7 ? pu1 : pu2, \
+                     omega)
+                    PSM_PAIR(1); PSM_PAIR(3); PSM_PAIR(5); PSM_PAIR(7); PSM_PAIR(9);
+                    PSM_PAIR(11); PSM_PAIR(13); PSM_PAIR(15); PSM_PAIR(17);
+#undef PSM_PAIR
+                } else {
+                    hx = (R)2 * jx - Ux; hy = (R)2 * jy - Uy; hz = (R)2 * jz - Uz;
+                    // slot terms with U_p(x) of eq. (20)
+                    R Bt = 0, A0 = 0, Mxx = 0, Myy = 0, Mzz = 0, Mxy = 0, Mxz = 0, Myz = 0, Px = 0, Py = 0, Pz = 0;
+                    if (c0 >= 0) {
+                        double dx = min_image(cxc - s_px[c0], Lx, hLx), dy = min_image(cyc - s_py[c0], Ly, hLy),
+                               dz = min_image(czc - s_pz[c0], Lz, hLz), vx, vy, vz;
+                        particle_velocity(c0, dx, dy, dz, s_ux, s_uy, s_uz, s_ox, s_oy, s_oz, vx, vy, vz);
+                        R Vx = (R)vx, Vy = (R)vy, Vz = (R)vz, Bs = (R)B0;
+                        Bt = Bs;
+                        A0 = Bs * (rho - (R)1.5 * (Vx * Vx + Vy * Vy + Vz * Vz));
+                        Px = Bs * Vx; Py = Bs * Vy; Pz = Bs * Vz;
+                        Mxx = Px * Vx; Myy = Py * Vy; Mzz = Pz * Vz;
+                        Mxy = Px * Vy; Mxz = Px * Vz; Myz = Py * Vz;
+                    }
+                    if (c1 >= 0) {
+                        double dx = min_image(cxc - s_px[c1], Lx, hLx), dy = min_image(cyc - s_py[c1], Ly, hLy),
+                               dz = min_image(czc - s_pz[c1], Lz, hLz), vx, vy, vz;
+                        particle_velocity(c1, dx, dy, dz, s_ux, s_uy, s_uz, s_ox, s_oy, s_oz, vx, vy, vz);
+                        R Vx = (R)vx, Vy = (R)vy, Vz = (R)vz, Bs = (R)B1;
+                        Bt = Bt + Bs;
+                        A0 = A0 + Bs * (rho - (R)1.5 * (Vx * Vx + Vy * Vy + Vz * Vz));
+                        R qx = Bs * Vx, qy = Bs * Vy, qz = Bs * Vz;
+                        Px = Px + qx; Py = Py + qy; Pz = Pz + qz;
+                        Mxx = Mxx + qx * Vx; Myy = Myy + qy * Vy; Mzz = Mzz + qz * Vz;
+                        Mxy = Mxy + qx * Vy; Mxz = Mxz + qx * Vz; Myz = Myz + qy * Vz;
+                    }
+                    const R omB = (R)1 - Bt;
+                    {
+                        constexpr R w = (R)W0;
+                        R s0 = w * base;
+                        R t0 = omega * (s0 - f[0]) - pu0;
+                        f[0] = (f[0] + omB * t0) + (w * A0 - Bt * s0);
+                    }
+#define PSM_PAIR(Q)                                                                                       \
+    pair_psm<R, Q>(f[Q], f[Q + 1], base, Ux, Uy, Uz, (R)bx.fa[Q / 2], (R)bx.fs[Q / 2], Q < 7 ? pu1 : pu2, omega, \
+                   Bt, omB, A0, Mxx, Myy, Mzz, Mxy, Mxz, Myz, Px, Py, Pz)
+                    PSM_PAIR(1); PSM_PAIR(3); PSM_PAIR(5); PSM_PAIR(7); PSM_PAIR(9);
+                    PSM_PAIR(11); PSM_PAIR(13); PSM_PAIR(15); PSM_PAIR(17);
+#undef PSM_PAIR
+                }
+                const long long n = xs + r00;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    S::storeb(db + q * qsb, (unsigned)n * (unsigned)sizeof(T), f[q], kp.h_scale);
+            }
+
+            // 5. force and torque of eqs. (21)-(22): sum_q C^solid_{q,s} c_qbar
+            // = 2 j - U - U_p(x) per slot (first moment of eq. 19); per-sphere
+            // wave sums accumulated per wave in LDS in a fixed order.
+            if (psm_wave) {
+                int pend0 = lane_ok ? c0 : -1, pend1 = lane_ok ? c1 : -1;
+                while (true) {
+                    unsigned long long live = __ballot(pend0 >= 0 || pend1 >= 0);
+                    if (live == 0ull) break;
+                    int leader = __ffsll((long long)live) - 1;
+                    int mine = pend0 >= 0 ? pend0 : pend1;
+                    int c = __shfl(mine, leader, 64);
+                    double Bs = 0.0;
+                    if (pend0 == c) { Bs = B0; pend0 = -1; }
+                    else if (pend1 == c) { Bs = B1; pend1 = -1; }
+                    double v[6] = {0, 0, 0, 0, 0, 0};
+                    if (Bs != 0.0) {
+                        double dx = min_image(cxc - s_px[c], Lx, hLx), dy = min_image(cyc - s_py[c], Ly, hLy),
+                               dz = min_image(czc - s_pz[c], Lz, hLz), vx, vy, vz;
+                        particle_velocity(c, dx, dy, dz, s_ux, s_uy, s_uz, s_ox, s_oy, s_oz, vx, vy, vz);
+                        R Vx = (R)vx, Vy = (R)vy, Vz = (R)vz;
+                        v[0] = Bs * (double)(hx - Vx);
+                        v[1] = Bs * (double)(hy - Vy);
+                        v[2] = Bs * (double)(hz - Vz);
+                        v[3] = dy * v[2] - dz * v[1];
+                        v[4] = dz * v[0] - dx * v[2];
+                        v[5] = dx * v[1] - dy * v[0];
+                    }
+#pragma unroll
+                    for (int k6 = 0; k6 < 6; ++k6) {
+                        double sum = wave_sum(v[k6]);
+                        if (lane == 0) s_acc[wave][k6][c] += sum;
+                    }
+                }
+            }
+        }
+
+        __syncthreads();
+        if (nc > 0) {
+            for (int i = tid; i < nc * 6; i += WG) {
+                int c = i / 6, k6 = i - 6 * c;
+                double s = 0.0;
+#pragma unroll
+                for (int w = 0; w < NWAVE; ++w) s += s_acc[w][k6][c];
+                kp.partial[(long long)(e0 + c) * 6 + k6] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-sphere force/torque: sum the tile partials of every tile of the
+// sphere's bounding box, in a fixed tile order (deterministic).
+__global__ void k_reduce_forces(ReduceParams rp) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= rp.P_total) return;
+    int b = rp.part_box[p];
+    const BoxDev& bx = rp.boxes[b];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    if (p - bx.part_base < bx.np) {
+        int lo, hi;
+        aabb_cells(rp.P.x[p], rp.P.r[p], lo, hi);
+        AxisTiles ax = axis_tiles(lo, hi, bx.nx, rp.ts.tx, bx.ntx);
+        aabb_cells(rp.P.y[p], rp.P.r[p], lo, hi);
+        AxisTiles ay = axis_tiles(lo, hi, bx.ny, rp.ts.ty, bx.nty);
+        aabb_cells(rp.P.z[p], rp.P.r[p], lo, hi);
+        AxisTiles az = axis_tiles(lo, hi, bx.nz, rp.ts.tz, bx.ntz);
+        int nzt = az.count(), nyt = ay.count(), nxt = ax.count();
+        for (int kz = 0; kz < nzt; ++kz)
+            for (int ky = 0; ky < nyt; ++ky)
+                for (int kx = 0; kx < nxt; ++kx) {
+                    int t = bx.tile_base + ax.at(kx) + bx.ntx * (ay.at(ky) + bx.nty * az.at(kz));
+                    int e0 = rp.tile_off[t], e1 = rp.tile_off[t + 1];
+                    for (int e = e0; e < e1; ++e)
+                        if (rp.tile_pid[e] == p) {
+                            for (int k = 0; k < 6; ++k) acc[k] += rp.partial[(long long)e * 6 + k];
+                            break;
+                        }
+                }
+    }
+    for (int k = 0; k < 6; ++k) rp.P.acc[(long long)p * 6 + k] = acc[k];
+}
+
+// ---------------------------------------------------------------------------
+// Tile binning (the paper's sub-block particle lists, built on the device):
+// count -> exclusive scan -> fill.
+template <bool FILL>
+__global__ void k_bin(BinParams bp) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= bp.P_total) return;
+    int b = bp.part_box[p];
+    const BoxDev& bx = bp.boxes[b];
+    if (p - bx.part_base >= bx.np) return;
+    int lo, hi;
+    aabb_cells(bp.P.x[p], bp.P.r[p], lo, hi);
+    AxisTiles ax = axis_tiles(lo, hi, bx.nx, bp.ts.tx, bx.ntx);
+    aabb_cells(bp.P.y[p], bp.P.r[p], lo, hi);
+    AxisTiles ay = axis_tiles(lo, hi, bx.ny, bp.ts.ty, bx.nty);
+    aabb_cells(bp.P.z[p], bp.P.r[p], lo, hi);
+    AxisTiles az = axis_tiles(lo, hi, bx.nz, bp.ts.tz, bx.ntz);
+    int nzt = az.count(), nyt = ay.count(), nxt = ax.count();
+    for (int kz = 0; kz < nzt; ++kz)
+        for (int ky = 0; ky < nyt; ++ky)
+            for (int kx = 0; kx < nxt; ++kx) {
+                int t = bx.tile_base + ax.at(kx) + bx.ntx * (ay.at(ky) + bx.nty * az.at(kz));
+                if (!FILL) {
+                    atomicAdd(&bp.tile_cnt[t], 1);
+                } else {
+                    int pos = atomicSub(&bp.tile_cnt[t], 1) - 1;
+                    bp.tile_pid[bp.tile_off[t] + pos] = p;
+                }
+            }
+}
+
+__global__ void k_fill_int(int* a, long long n, int v) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) a[i] = v;
+}
+
+// Exclusive scan of cnt[0..n) into off[0..n]; one workgroup of 1024 threads.
+// stats[0] = largest count, stats[1] = total.
+__global__ __launch_bounds__(1024) void k_scan(const int* cnt, int* off, int n, int* stats) {
+    __shared__ int s_part[1024];
+    __shared__ int s_carry, s_max;
+    const int tid = threadIdx.x;
+    if (tid == 0) { s_carry = 0; s_max = 0; }
+    __syncthreads();
+    int mymax = 0;
+    for (int base = 0; base < n; base += 1024 * 4) {
+        int v[4], loc = 0;
+        for (int k = 0; k < 4; ++k) {
+            int i = base + tid * 4 + k;
+            v[k] = i < n ? cnt[i] : 0;
+            mymax = v[k] > mymax ? v[k] : mymax;
+            loc += v[k];
+        }
+        s_part[tid] = loc;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            int add = tid >= d ? s_part[tid - d] : 0;
+            __syncthreads();
+            s_part[tid] += add;
+            __syncthreads();
+        }
+        int run = s_carry + (s_part[tid] - loc);
+        for (int k = 0; k < 4; ++k) {
+            int i = base + tid * 4 + k;
+            if (i < n) off[i] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        if (tid == 1023) s_carry += s_part[1023];
+        __syncthreads();
+    }
+    atomicMax(&s_max, mymax);
+    __syncthreads();
+    if (tid == 0) {
+        off[n] = s_carry;
+        stats[0] = s_max;
+        stats[1] = s_carry;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// State I/O. Canonical f(x,t) = grid[q][x - c_q] (pull storage).
+
+template <class S>
+__global__ void k_set_pdfs(BoxDev bx, int parity, const double* __restrict__ f, float scale) {
+    long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= bx.N) return;
+    int x = n % bx.nx, y = (n / bx.nx) % bx.ny, z = n / ((long long)bx.nx * bx.ny);
+    typename S::T* g = (typename S::T*)bx.grid[parity];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        int xs = x + CX[q], ys = y + CY[q], zs = z + CZ[q];
+        xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
+        ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
+        zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
+        double v = f[(long long)q * bx.N + xs + (long long)bx.nx * (ys + (long long)bx.ny * zs)];
+        if (S::DEV) v -= wq(q);
+        g[q * bx.qstride + n] = S::from_f64(v, scale);
+    }
+}
+
+template <class S>
+__global__ void k_set_equilibrium(BoxDev bx, int parity, const double* __restrict__ rho,
+                                  const double* __restrict__ u, float scale) {
+    long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= bx.N) return;
+    int x = n % bx.nx, y = (n / bx.nx) % bx.ny, z = n / ((long long)bx.nx * bx.ny);
+    typename S::T* g = (typename S::T*)bx.grid[parity];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        int xs = x + CX[q], ys = y + CY[q], zs = z + CZ[q];
+        xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
+        ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
+        zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
+        long long s = xs + (long long)bx.nx * (ys + (long long)bx.ny * zs);
+        double r = rho ? rho[s] : 1.0;
+        double vx = u[s], vy = u[bx.N + s], vz = u[2LL * bx.N + s];
+        double cv = CX[q] * vx + CY[q] * vy + CZ[q] * vz;
+        double vv = vx * vx + vy * vy + vz * vz;
+        double rr = S::DEV ? r - 1.0 : r;   // deviation form: E_q - w_q
+        double e = wq(q) * (rr + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
+        g[q * bx.qstride + n] = S::from_f64(e, scale);
+    }
+}
+
+template <class S>
+__global__ void k_get_pdfs(BoxDev bx, int parity, double* __restrict__ f, float inv) {
+    long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= bx.N) return;
+    int x = n % bx.nx, y = (n / bx.nx) % bx.ny, z = n / ((long long)bx.nx * bx.ny);
+    const typename S::T* g = (const typename S::T*)bx.grid[parity];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        int xs = x - CX[q], ys = y - CY[q], zs = z - CZ[q];
+        xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
+        ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
+        zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
+        double v = S::to_f64(g[q * bx.qstride + xs + (long long)bx.nx * (ys + (long long)bx.ny * zs)], inv);
+        if (S::DEV) v += wq(q);
+        f[(long long)q * bx.N + n] = v;
+    }
+}
+
+template <class S>
+__global__ void k_get_pdfs_at(BoxDev bx, int parity, const int* __restrict__ cells, int ncells,
+                              double* __restrict__ out, float inv) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncells) return;
+    long long n = cells[i];
+    int x = n % bx.nx, y = (n / bx.nx) % bx.ny, z = n / ((long long)bx.nx * bx.ny);
+    const typename S::T* g = (const typename S::T*)bx.grid[parity];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        int xs = x - CX[q], ys = y - CY[q], zs = z - CZ[q];
+        xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
+        ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
+        zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
+        double v = S::to_f64(g[q * bx.qstride + xs + (long long)bx.nx * (ys + (long long)bx.ny * zs)], inv);
+        if (S::DEV) v += wq(q);
+        out[(long long)q * ncells + i] = v;
+    }
+}
+
+template <class S>
+__global__ void k_macroscopic(BoxDev bx, int parity, double* __restrict__ rho, double* __restrict__ u,
+                              float inv) {
+    long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= bx.N) return;
+    int x = n % bx.nx, y = (n / bx.nx) % bx.ny, z = n / ((long long)bx.nx * bx.ny);
+    const typename S::T* g = (const typename S::T*)bx.grid[parity];
+    double r = 0, j[3] = {0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        int xs = x - CX[q], ys = y - CY[q], zs = z - CZ[q];
+        xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
+        ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
+        zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
+        double v = S::to_f64(g[q * bx.qstride + xs + (long long)bx.nx * (ys + (long long)bx.ny * zs)], inv);
+        if (S::DEV) v += wq(q);
+        r += v;
+        j[0] += v * CX[q]; j[1] += v * CY[q]; j[2] += v * CZ[q];
+    }
+    rho[n] = r;
+    u[n] = j[0] + 0.5 * bx.g[0];
+    u[bx.N + n] = j[1] + 0.5 * bx.g[1];
+    u[2LL * bx.N + n] = j[2] + 0.5 * bx.g[2];
+}
+
+// Dense two-slot solid fractions of one box (readout and overflow count),
+// through the same candidate lists and mapping function as the step kernel.
+__global__ void k_map_dense(BoxDev bx, int box_tile_base_unused, Particles P, const int* __restrict__ tile_off,
+                            const int* __restrict__ tile_pid, TileShape ts, double* __restrict__ B,
+                            int* __restrict__ pid, unsigned long long* dropped) {
+    long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= bx.N) return;
+    int x = n % bx.nx, y = (n / bx.nx) % bx.ny, z = n / ((long long)bx.nx * bx.ny);
+    int t = bx.tile_base + x / ts.tx + bx.ntx * (y / ts.ty + bx.nty * (z / ts.tz));
+    int e0 = tile_off[t], e1 = tile_off[t + 1];
+    Slots sl;
+    slots_init(sl);
+    for (int e = e0; e < e1; ++e) {
+        int p = tile_pid[e];
+        double dx = min_image((x + 0.5) - P.x[p], bx.L[0], bx.halfL[0]);
+        double dy = min_image((y + 0.5) - P.y[p], bx.L[1], bx.halfL[1]);
+        double dz = min_image((z + 0.5) - P.z[p], bx.L[2], bx.halfL[2]);
+        double b = bx.mapping == 0 ? overlap_linear(dx, dy, dz, P.r[p], P.fr[p])
+                                   : overlap_subsample(dx, dy, dz, P.r[p], bx.nsub, bx.sub_off, bx.reach);
+        if (b > 0.0) slots_insert(sl, p, p, b);
+    }
+    slots_finish(sl);
+    if (B) {
+        B[n] = sl.c0 >= 0 ? sl.B0 : 0.0;
+        B[bx.N + n] = sl.c1 >= 0 ? sl.B1 : 0.0;
+    }
+    if (pid) {
+        pid[n] = sl.c0 >= 0 ? sl.c0 - bx.part_base : -1;
+        pid[bx.N + n] = sl.c1 >= 0 ? sl.c1 - bx.part_base : -1;
+    }
+    if (sl.dropped) atomicAdd(dropped, (unsigned long long)sl.dropped);
+}
+
+// FP64 mass and momentum of the stored state (a permutation of f(x,t)):
+// per-block partial sums, then one block adds them in a fixed order.
+template <class S>
+__global__ __launch_bounds__(256) void k_stats_partial(BoxDev bx, int parity, float inv, double* __restrict__ part) {
+    __shared__ double s[4][256];
+    const typename S::T* g = (const typename S::T*)bx.grid[parity];
+    double m = 0, px = 0, py = 0, pz = 0;
+    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < bx.N;
+         n += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            double v = S::to_f64(g[q * bx.qstride + n], inv);
+            if (S::DEV) v += wq(q);
+            m += v;
+            px += v * CX[q]; py += v * CY[q]; pz += v * CZ[q];
+        }
+    }
+    s[0][threadIdx.x] = m; s[1][threadIdx.x] = px; s[2][threadIdx.x] = py; s[3][threadIdx.x] = pz;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d)
+            for (int k = 0; k < 4; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void k_stats_final(const double* part, int nblk, double* out) {
+    if (threadIdx.x < 4) {
+        double s = 0;
+        for (int b = 0; b < nblk; ++b) s += part[b * 4 + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// Plain streaming copy (bandwidth reference).
+__global__ __launch_bounds__(256) void k_stream_copy(const double2* __restrict__ a, double2* __restrict__ b,
+                                                     long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) b[i] = a[i];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (called by the engine).
+
+static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <int MAP>
+static hipError_t launch_step_map(int storage, const StepParams& kp, int grid, hipStream_t st) {
+    switch (storage) {
+        case 0: hipLaunchKernelGGL((k_psm_step<St64, MAP>), dim3(grid), dim3(WG), 0, st, kp); break;
+        case 1: hipLaunchKernelGGL((k_psm_step<St32, MAP>), dim3(grid), dim3(WG), 0, st, kp); break;
+        default: hipLaunchKernelGGL((k_psm_step<St16, MAP>), dim3(grid), dim3(WG), 0, st, kp); break;
+    }
+    return hipGetLastError();
+}
+
+// map: 0 when every box uses the linear approximation, 1 if any box samples.
+hipError_t launch_step(int storage, int map, const StepParams& kp, int grid, hipStream_t st) {
+    return map ? launch_step_map<1>(storage, kp, grid, st) : launch_step_map<0>(storage, kp, grid, st);
+}
+
+template <int MAP>
+static int blocks_per_cu_map(int storage) {
+    int nb = 0;
+    switch (storage) {
+        case 0: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_psm_step<St64, MAP>, WG, 0); break;
+        case 1: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_psm_step<St32, MAP>, WG, 0); break;
+        default: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_psm_step<St16, MAP>, WG, 0); break;
+    }
+    return nb > 0 ? nb : 1;
+}
+
+int step_blocks_per_cu(int storage, int map) {
+    return map ? blocks_per_cu_map<1>(storage) : blocks_per_cu_map<0>(storage);
+}
+
+hipError_t launch_reduce(const ReduceParams& rp, hipStream_t st) {
+    if (rp.P_total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_forces, dim3(blocks_for(rp.P_total, 128)), dim3(128), 0, st, rp);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin(const BinParams& bp, int* stats, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(bp.T_total, 256) > 4096 ? 4096 : blocks_for(bp.T_total, 256)),
+                       dim3(256), 0, st, bp.tile_cnt, (long long)bp.T_total, 0);
+    if (bp.P_total > 0)
+        hipLaunchKernelGGL(k_bin<false>, dim3(blocks_for(bp.P_total, 128)), dim3(128), 0, st, bp);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, bp.tile_cnt, bp.tile_off, bp.T_total, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_fill(const BinParams& bp, hipStream_t st) {
+    if (bp.P_total > 0)
+        hipLaunchKernelGGL(k_bin<true>, dim3(blocks_for(bp.P_total, 128)), dim3(128), 0, st, bp);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_pdfs(int storage, const BoxDev& bx, int parity, const double* f, float scale,
+                           hipStream_t st) {
+    unsigned g = blocks_for(bx.N, 256);
+    switch (storage) {
+        case 0: hipLaunchKernelGGL(k_set_pdfs<St64>, dim3(g), dim3(256), 0, st, bx, parity, f, scale); break;
+        case 1: hipLaunchKernelGGL(k_set_pdfs<St32>, dim3(g), dim3(256), 0, st, bx, parity, f, scale); break;
+        default: hipLaunchKernelGGL(k_set_pdfs<St16>, dim3(g), dim3(256), 0, st, bx, parity, f, scale); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_set_equilibrium(int storage, const BoxDev& bx, int parity, const double* rho, const double* u,
+                                  float scale, hipStream_t st) {
+    unsigned g = blocks_for(bx.N, 256);
+    switch (storage) {
+        case 0: hipLaunchKernelGGL(k_set_equilibrium<St64>, dim3(g), dim3(256), 0, st, bx, parity, rho, u, scale); break;
+        case 1: hipLaunchKernelGGL(k_set_equilibrium<St32>, dim3(g), dim3(256), 0, st, bx, parity, rho, u, scale); break;
+        default: hipLaunchKernelGGL(k_set_equilibrium<St16>, dim3(g), dim3(256), 0, st, bx, parity, rho, u, scale); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_get_pdfs(int storage, const BoxDev& bx, int parity, double* f, float inv, hipStream_t st) {
+    unsigned g = blocks_for(bx.N, 256);
+    switch (storage) {
+        case 0: hipLaunchKernelGGL(k_get_pdfs<St64>, dim3(g), dim3(256), 0, st, bx, parity, f, inv); break;
+        case 1: hipLaunchKernelGGL(k_get_pdfs<St32>, dim3(g), dim3(256), 0, st, bx, parity, f, inv); break;
+        default: hipLaunchKernelGGL(k_get_pdfs<St16>, dim3(g), dim3(256), 0, st, bx, parity, f, inv); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_get_pdfs_at(int storage, const BoxDev& bx, int parity, const int* cells, int ncells, double* out,
+                              float inv, hipStream_t st) {
+    unsigned g = blocks_for(ncells, 256);
+    switch (storage) {
+        case 0: hipLaunchKernelGGL(k_get_pdfs_at<St64>, dim3(g), dim3(256), 0, st, bx, parity, cells, ncells, out, inv); break;
+        case 1: hipLaunchKernelGGL(k_get_pdfs_at<St32>, dim3(g), dim3(256), 0, st, bx, parity, cells, ncells, out, inv); break;
+        default: hipLaunchKernelGGL(k_get_pdfs_at<St16>, dim3(g), dim3(256), 0, st, bx, parity, cells, ncells, out, inv); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_macroscopic(int storage, const BoxDev& bx, int parity, double* rho, double* u, float inv,
+                              hipStream_t st) {
+    unsigned g = blocks_for(bx.N, 256);
+    switch (storage) {
+        case 0: hipLaunchKernelGGL(k_macroscopic<St64>, dim3(g), dim3(256), 0, st, bx, parity, rho, u, inv); break;
+        case 1: hipLaunchKernelGGL(k_macroscopic<St32>, dim3(g), dim3(256), 0, st, bx, parity, rho, u, inv); break;
+        default: hipLaunchKernelGGL(k_macroscopic<St16>, dim3(g), dim3(256), 0, st, bx, parity, rho, u, inv); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_map_dense(const BoxDev& bx, const Particles& P, const int* tile_off, const int* tile_pid,
+                            TileShape ts, double* B, int* pid, unsigned long long* dropped, hipStream_t st) {
+    hipLaunchKernelGGL(k_map_dense, dim3(blocks_for(bx.N, 256)), dim3(256), 0, st, bx, 0, P, tile_off, tile_pid, ts,
+                       B, pid, dropped);
+    return hipGetLastError();
+}
+
+int stats_blocks() { return 1024; }
+
+hipError_t launch_stats(int storage, const BoxDev& bx, int parity, float inv, double* part, double* out,
+                        hipStream_t st) {
+    int nb = stats_blocks();
+    switch (storage) {
+        case 0: hipLaunchKernelGGL(k_stats_partial<St64>, dim3(nb), dim3(256), 0, st, bx, parity, inv, part); break;
+        case 1: hipLaunchKernelGGL(k_stats_partial<St32>, dim3(nb), dim3(256), 0, st, bx, parity, inv, part); break;
+        default: hipLaunchKernelGGL(k_stats_partial<St16>, dim3(nb), dim3(256), 0, st, bx, parity, inv, part); break;
+    }
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, st, part, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st) {
+    long long n = (long long)(bytes / 16);
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    long long blocks = (n + 255) / 256;
+    long long cap = (long long)ncu * 16;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)(blocks < cap ? blocks : cap)), dim3(256), 0, st,
+                       (const double2*)src, (double2*)dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace psm

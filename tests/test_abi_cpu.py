@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point declared in include/psm.h, and rejects bad arguments with
+PSM_EINVAL before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2303_11811_amd as psm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "psm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(psm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) >= 20
+    L = psm.lib()
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in psm._SIGS, f"binding lacks {n}"
+
+
+def test_workspace_size_scales_with_storage():
+    d = [psm.make_desc(64, 48, 40, 0.6, max_particles=10, max_radius=5.0)]
+    s64 = psm.psm_workspace_size(d, psm.PSM_FP64)
+    s32 = psm.psm_workspace_size(d, psm.PSM_FP32DEV)
+    s16 = psm.psm_workspace_size(d, psm.PSM_FP16DEV)
+    grid = 2 * 19 * 64 * 48 * 40
+    assert s64 - s32 == grid * 4 and s32 - s16 == grid * 2
+    assert s64 > grid * 8
+
+
+@pytest.mark.parametrize("desc,msg", [
+    (dict(nx=3, ny=8, nz=8, tau=0.6), "dimension"),
+    (dict(nx=8, ny=8, nz=8, tau=0.5), "tau"),
+    (dict(nx=8, ny=8, nz=8, tau=float("nan")), "tau"),
+    (dict(nx=16, ny=16, nz=16, tau=0.6, max_particles=2, max_radius=0.5), "max_radius"),
+    (dict(nx=16, ny=16, nz=16, tau=0.6, max_particles=2, max_radius=7.0), "2*(max_radius+1)+2"),
+    (dict(nx=16, ny=16, nz=16, tau=0.6, mapping=7), "mapping"),
+    (dict(nx=16, ny=16, nz=16, tau=0.6, mapping=1, subsample_n=0), "subsample_n"),
+    (dict(nx=16, ny=16, nz=16, tau=0.6, max_particles=-1), "max_particles"),
+])
+def test_invalid_descriptors(desc, msg):
+    with pytest.raises(psm.PsmError) as e:
+        psm.psm_workspace_size([psm.make_desc(**desc)], psm.PSM_FP64)
+    assert e.value.code == psm.PSM_EINVAL and msg in str(e.value)
+
+
+def test_invalid_storage_and_empty():
+    with pytest.raises(psm.PsmError):
+        psm.psm_workspace_size([psm.make_desc(8, 8, 8, 0.6)], 7)
+    out = ctypes.c_size_t(0)
+    assert psm.lib().psm_workspace_size(None, 0, 0, ctypes.byref(out)) == psm.PSM_EINVAL
+
+
+def test_create_rejects_before_touching_the_gpu():
+    d = [psm.make_desc(8, 8, 8, 0.6)]
+    need = psm.psm_workspace_size(d, psm.PSM_FP64)
+    for ws, nbytes, msg in [(0, need, "NULL"), (256 + 8, need, "aligned"), (1 << 20, need - 1, "needs")]:
+        with pytest.raises(psm.PsmError) as e:
+            psm.psm_create(d, psm.PSM_FP64, 0.0, 0, ws, nbytes)
+        assert e.value.code == psm.PSM_EINVAL and msg in str(e.value)
+    with pytest.raises(psm.PsmError) as e:
+        psm.psm_create(d, psm.PSM_FP16DEV, 3.0, 0, 1 << 20, 1 << 40)
+    assert "power of two" in str(e.value)
+
+
+def test_null_context_calls():
+    L = psm.lib()
+    assert L.psm_step(None, 1) == psm.PSM_EINVAL
+    assert L.psm_destroy(None) == psm.PSM_EINVAL
+    assert L.psm_set_graph(None, 1) == psm.PSM_EINVAL
+    assert L.psm_get_forces(None, 0, None, None) == psm.PSM_EINVAL
+    assert "NULL" in psm.psm_last_error() or "ctx" in psm.psm_last_error()
+
+
+def test_stream_copy_argument_checks():
+    L = psm.lib()
+    assert L.psm_stream_copy(None, None, 16, None) == psm.PSM_EINVAL
+    assert L.psm_stream_copy(ctypes.c_void_p(256), ctypes.c_void_p(4096), 15, None) == psm.PSM_EINVAL
+    assert L.psm_stream_copy(ctypes.c_void_p(256), ctypes.c_void_p(264), 64, None) == psm.PSM_EINVAL

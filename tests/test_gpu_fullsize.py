@@ -1,0 +1,130 @@
+"""Full-size check of the benchmark workload: 512^3 periodic box, FP64,
+tau 0.55, body force 1e-6, 3204 spheres of diameter 20, in the launch shape
+the autotuner picks (as bench.py does).
+
+The oracle cannot run 1.3e8 cells, so it checks what it can compute one by
+one from the engine's own state at step t:
+  * sampled cells: f(x, t+1) = f~_q(x - c_q, t) from the oracle's per-cell
+    mapping (brute force over all spheres) and collision of the 19 source
+    cells -- to 1e-12 relative;
+  * sampled spheres: F, T of eqs. (21)-(22) summed by the oracle over the
+    sphere's bounding box -- to the FP64 force tolerance;
+and, at full size, the exact momentum balance of every step:
+  sum_x j(t+1) - sum_x j(t) = f_ext sum_x (1 - B) - sum_p F_p.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2303_11811_amd as psm
+from paper_2303_11811_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+CX = np.array([0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0])
+CY = np.array([0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1])
+CZ = np.array([0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1])
+
+
+@pytest.fixture(scope="module")
+def fullsize():
+    import torch
+
+    spec = inputs.paper_scale(n=512, seed=1)
+    print(f"[case] fullsize 512^3 spheres={len(spec.r)}", flush=True)
+    eng = psm.Engine([psm.desc_from_spec(spec)], storage=psm.PSM_FP64)
+    with torch.cuda.stream(eng.stream):
+        u0 = torch.zeros((3, spec.N), dtype=torch.float64, device=eng.device)
+    eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+    eng.set_equilibrium(0, u0)
+    eng.autotune(trial_steps=2)
+    eng.set_equilibrium(0, u0)
+    del u0
+    eng.step(5)
+    yield spec, eng
+    eng.close()
+
+
+def _idx(i, j, k, n):
+    return (i % n) + n * ((j % n) + n * (k % n))
+
+
+def test_sampled_cells_one_step(fullsize):
+    spec, eng = fullsize
+    n = spec.dims[0]
+    rng = np.random.default_rng(99)
+    # half the samples near sphere surfaces, half anywhere
+    pick = rng.integers(0, len(spec.r), 48)
+    cells = []
+    for p in pick:
+        d = rng.normal(size=3)
+        d *= (spec.r[p] + rng.uniform(-1.5, 0.8)) / np.linalg.norm(d)
+        c = np.floor(spec.x[p] + d).astype(int) % n
+        cells.append(tuple(c))
+    cells += [tuple(v) for v in rng.integers(0, n, (48, 3))]
+    src = [[(i - CX[q], j - CY[q], k - CZ[q]) for q in range(19)] for (i, j, k) in cells]
+    flat_src = [s for row in src for s in row]
+    f_t = eng.get_pdfs_at(0, [_idx(*s, n) for s in flat_src]).cpu().numpy()
+    eng.step(1)
+    f_t1 = eng.get_pdfs_at(0, [_idx(i, j, k, n) for (i, j, k) in cells]).cpu().numpy()
+    box = oracle.Box(n, n, n, tau=spec.tau, fext=spec.fext)
+    frv = oracle.fr(spec.r)
+    for a, (i, j, k) in enumerate(cells):
+        for q in range(19):
+            s = flat_src[a * 19 + q]
+            si, sj, sk = s[0] % n, s[1] % n, s[2] % n
+            ns, pid, B, _ = oracle.map_cell(box, si, sj, sk, spec.x, spec.r, frv)
+            ft, _ = oracle.collide_cell(box, si, sj, sk, f_t[:, a * 19 + q], pid[:ns], B[:ns],
+                                        spec.x, spec.U, spec.Om)
+            assert abs(f_t1[q, a] - ft[q]) <= 1e-12 * abs(ft[q]), (i, j, k, q, f_t1[q, a], ft[q])
+
+
+def test_sampled_sphere_forces(fullsize):
+    spec, eng = fullsize
+    n = spec.dims[0]
+    box = oracle.Box(n, n, n, tau=spec.tau, fext=spec.fext)
+    frv = oracle.fr(spec.r)
+    rng = np.random.default_rng(7)
+    ps = rng.choice(len(spec.r), 2, replace=False)
+    # state at t for every cell of the spheres' boxes, then one step
+    cell_sets = {}
+    for p in ps:
+        lo = np.floor(spec.x[p] - (spec.r[p] + 1)).astype(int)
+        hi = np.floor(spec.x[p] + (spec.r[p] + 1)).astype(int)
+        rng3 = [np.arange(lo[a], hi[a] + 1) for a in range(3)]
+        K, J, I = np.meshgrid(rng3[2], rng3[1], rng3[0], indexing="ij")
+        cell_sets[p] = np.stack([I.ravel() % n, J.ravel() % n, K.ravel() % n], axis=1)
+    f_sets = {p: eng.get_pdfs_at(0, [_idx(*c, n) for c in cs]).cpu().numpy() for p, cs in cell_sets.items()}
+    eng.step(1)
+    F, T = eng.get_forces(0)
+    for p in ps:
+        Fo, To, A = np.zeros(3), np.zeros(3), 0.0
+        for a, (i, j, k) in enumerate(cell_sets[p]):
+            ns, pid, B, _ = oracle.map_cell(box, i, j, k, spec.x, spec.r, frv)
+            if p not in pid[:ns]:
+                continue
+            _, g = oracle.collide_cell(box, i, j, k, f_sets[p][:, a], pid[:ns], B[:ns], spec.x, spec.U, spec.Om)
+            s = list(pid[:ns]).index(p)
+            d = np.array([i + 0.5, j + 0.5, k + 0.5]) - spec.x[p]
+            d -= n * np.round(d / n)
+            Bg = B[s] * g[s]
+            Fo += Bg
+            To += np.cross(d, Bg)
+            A += B[s] * np.linalg.norm(g[s])
+        assert np.linalg.norm(F[p] - Fo) <= 1e-12 * np.linalg.norm(Fo) + 1e-14 * A
+        assert np.linalg.norm(T[p] - To) <= 1e-12 * np.linalg.norm(To) + 1e-14 * A * (spec.r[p] + 1)
+
+
+def test_momentum_balance_full_size(fullsize):
+    spec, eng = fullsize
+    g = np.array(spec.fext)
+    for _ in range(2):
+        _, P0, _ = eng.get_stats(0)
+        B, _ = eng.get_solid_fraction(0)
+        one_minus_B = float(spec.N - B.sum().item())
+        eng.step(1)
+        _, P1, _ = eng.get_stats(0)
+        F, _ = eng.get_forces(0)
+        expect = g * one_minus_B - F.sum(axis=0)
+        scale = np.abs(g).max() * spec.N + np.abs(F).sum()
+        assert np.all(np.abs((P1 - P0) - expect) <= 1e-9 * scale), (P1 - P0, expect)

@@ -1,0 +1,153 @@
+"""GPU-vs-oracle parity of the fused PSM-LBM step (FP64 storage), called
+through the C ABI. Tolerance for FP64: 1e-12 relative on PDFs, density and
+velocity; forces and torques to 1e-12 relative plus 1e-14 of the force's
+term magnitude (the two sides sum the same terms in different orders);
+solid-fraction slots: particle ids exact, fractions exact for sub-sampling
+and to 1e-15 for the linear approximation."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2303_11811_amd as psm
+from paper_2303_11811_amd import inputs
+from psm_cases import (assert_forces_close, assert_pdfs_close, initial_f, make_engine, run_engine,
+                       run_oracle)
+
+pytestmark = pytest.mark.gpu
+
+
+def _print_case(name, **kw):
+    print(f"[case] {name} {kw}", flush=True)
+
+
+def test_parity_32_subsample_100_steps():
+    """32^3, tau 0.6, Taylor-Green start, 8 spheres r=4 with 4^3 sampling."""
+    spec = inputs.parity_32(seed=0)
+    _print_case("parity_32", steps=100)
+    ref = run_oracle(spec, 100)
+    f, F, T, B, pid, eng = run_engine(spec, 100)
+    assert_pdfs_close(f, ref.f, 1e-12)
+    assert np.array_equal(pid, ref.pid)
+    assert np.array_equal(B, ref.B)
+    assert_forces_close(F, ref.F, ref.A)
+    assert_forces_close(T, ref.T, ref.A, lever=spec.r.max() + 1)
+    rho, u = eng.get_macroscopic(0)
+    rho_ref, u_ref = oracle.macroscopic(oracle.Box(*spec.dims, tau=spec.tau), ref.f)
+    assert np.allclose(rho.cpu().numpy(), rho_ref, rtol=1e-12, atol=0)
+    assert np.allclose(u.cpu().numpy(), u_ref, rtol=0, atol=1e-14)
+
+
+RAGGED = [
+    # dims, tiles (tx, ty, tz), particles, overlap
+    ((40, 36, 20), (64, 4, 4), 4, False),
+    ((37, 29, 23), (32, 8, 16), 5, False),
+    ((70, 21, 18), (16, 16, 2), 3, True),
+    ((33, 40, 27), (128, 2, 8), 6, True),
+    ((24, 24, 24), (256, 1, 32), 2, False),
+]
+
+
+@pytest.mark.parametrize("dims,tiles,npart,overlap", RAGGED)
+def test_parity_ragged_linear(dims, tiles, npart, overlap):
+    """Boxes that are not multiples of the tile, several tiles per axis,
+    body force, rotating spheres, overlapping spheres (renormalised slots)."""
+    spec = inputs.random_small(dims, npart, (2.5, 4.0), seed=sum(dims), tau=0.67,
+                               fext=(2e-5, -1e-5, 5e-6), vamp=0.01, omamp=0.002, overlap=overlap)
+    _print_case("ragged", dims=dims, tiles=tiles, n=len(spec.r))
+    steps = 12
+    ref = run_oracle(spec, steps)
+    f, F, T, B, pid, eng = run_engine(spec, steps, launch=tiles)
+    assert_pdfs_close(f, ref.f, 1e-12)
+    assert np.array_equal(pid, ref.pid)
+    assert np.max(np.abs(B - ref.B)) <= 1e-15
+    assert_forces_close(F, ref.F, ref.A)
+    assert_forces_close(T, ref.T, ref.A, lever=spec.r.max() + 1)
+    _, _, ov = eng.get_stats(0)
+    # overflow count of the current mapping equals the oracle's
+    assert ov == ref.overflow
+
+
+def test_parity_no_particles_with_force():
+    spec = inputs.random_small((48, 20, 12), 0, (2, 3), seed=3, tau=0.83, fext=(1e-5, 2e-6, -3e-6))
+    ref = run_oracle(spec, 30)
+    f, *_ = run_engine(spec, 30)
+    assert_pdfs_close(f, ref.f, 1e-12)
+
+
+def test_set_equilibrium_matches_oracle():
+    spec = inputs.random_small((20, 12, 9), 0, (2, 3), seed=8, tau=0.7, fext=(1e-4, 0, 0))
+    eng = make_engine([spec])
+    eng.set_equilibrium(0, spec.u0, spec.rho0)
+    f = eng.get_pdfs(0).cpu().numpy()
+    ref = initial_f(spec)
+    assert np.max(np.abs(f - ref)) <= 1e-16
+
+
+def test_batched_boxes_match_single_runs():
+    """Three boxes of different sizes, relaxation times, forces and particles
+    in one context advance exactly as the oracle advances each alone."""
+    specs = [inputs.random_small((32, 32, 32), 4, (3.0, 4.0), seed=11, tau=0.55),
+             inputs.random_small((48, 40, 36), 6, (3.0, 5.0), seed=12, tau=0.93, fext=(0, 3e-6, 0)),
+             inputs.random_small((20, 20, 20), 0, (2, 3), seed=13, tau=0.71)]
+    eng = make_engine(specs)
+    for b, s in enumerate(specs):
+        eng.set_pdfs(b, initial_f(s))
+        if s.n_particles:
+            eng.set_particles(b, s.x, s.r, s.U, s.Om)
+    eng.step(9)
+    for b, s in enumerate(specs):
+        ref = run_oracle(s, 9)
+        assert_pdfs_close(eng.get_pdfs(b).cpu().numpy(), ref.f, 1e-12)
+        if s.n_particles:
+            F, T = eng.get_forces(b)
+            assert_forces_close(F, ref.F, ref.A)
+            assert_forces_close(T, ref.T, ref.A, lever=s.r.max() + 1)
+
+
+def test_graph_replay_equals_eager_bitwise():
+    spec = inputs.random_small((40, 36, 28), 5, (3.0, 4.5), seed=21, tau=0.6, fext=(1e-5, 0, 0),
+                               omamp=0.002)
+    f_e, F_e, T_e, *_ = run_engine(spec, 20, graph=False)
+    f_g, F_g, T_g, *_ = run_engine(spec, 20, graph=True)
+    assert np.array_equal(f_e, f_g)
+    assert np.array_equal(F_e, F_g) and np.array_equal(T_e, T_g)
+    # replays interleaved with eager steps and syncs
+    f_m, F_m, _, _, _, eng = run_engine(spec, 13, graph=True)
+    eng.step(7)
+    f2 = eng.get_pdfs(0).cpu().numpy()
+    assert np.array_equal(f2, f_e)
+
+
+def test_deterministic_repeat():
+    spec = inputs.random_small((36, 36, 36), 6, (3.0, 5.0), seed=31, tau=0.7, omamp=0.003)
+    a = run_engine(spec, 10)
+    b = run_engine(spec, 10)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_stats_mass_and_momentum():
+    spec = inputs.random_small((30, 26, 22), 3, (2.5, 3.5), seed=41, tau=0.8, fext=(3e-5, 0, 1e-5))
+    ref = run_oracle(spec, 5)
+    f, F, T, B, pid, eng = run_engine(spec, 5)
+    mass, mom, ov = eng.get_stats(0)
+    c, _, _ = oracle.lattice()
+    assert abs(mass - ref.f.sum()) <= 1e-12 * ref.f.sum()
+    assert np.allclose(mom, (ref.f.T @ c.astype(float)).sum(0), rtol=1e-10, atol=1e-13)
+
+
+def test_tile_capacity_error_is_reported():
+    """More sphere candidates in one tile than the kernel stages is refused
+    with PSM_ECAPACITY, and the context keeps working."""
+    dims = (64, 64, 64)
+    rng = np.random.default_rng(5)
+    n = 80
+    x = np.column_stack([rng.uniform(20, 44, n), rng.uniform(20, 24, n), rng.uniform(30, 34, n)])
+    r = np.full(n, 1.5)
+    eng = psm.Engine([psm.make_desc(*dims, 0.7, max_particles=n, max_radius=2.0)])
+    eng.set_equilibrium(0, np.zeros((3, dims[0] * dims[1] * dims[2])))
+    eng.set_launch(256, 1, 32)
+    with pytest.raises(psm.PsmError) as e:
+        eng.set_particles(0, x, r, np.zeros((n, 3)))
+    assert e.value.code == psm.PSM_ECAPACITY
+    eng.set_particles(0, x[:4], r[:4], np.zeros((4, 3)))
+    eng.step(1)

@@ -149,6 +149,88 @@ def precision_errors(psm, torch, inputs, n=64, steps=1000):
     return out
 
 
+def run_batched(psm, torch, inputs, steps=500, nbox=64):
+    """64 independent uneven boxes in one persistent launch per step, FP32
+    deviation storage, replayed as captured 10-step HIP graphs."""
+    import numpy as np
+
+    specs = inputs.batched_boxes(nbox=nbox, seed=3)
+    descs = [psm.desc_from_spec(s, max_particles=max(s.n_particles, 1), max_radius=8.0) for s in specs]
+    eng = psm.Engine(descs, storage=psm.PSM_FP32DEV)
+    for b, s in enumerate(specs):
+        if s.n_particles:
+            eng.set_particles(b, s.x, s.r, s.U, s.Om)
+    for b, s in enumerate(specs):
+        eng.set_equilibrium(b, s.u0)
+    shape, _ = eng.autotune(trial_steps=10)
+    for b, s in enumerate(specs):
+        eng.set_equilibrium(b, s.u0)
+    eng.set_graph(True)
+    eng.step(20)
+    eng.synchronize()
+    t0 = time.perf_counter()
+    eng.step(steps)
+    eng.synchronize()
+    dt = time.perf_counter() - t0
+    cells = sum(s.N for s in specs)
+    mass_ok = all(np.isfinite(eng.get_stats(b)[0]) for b in range(len(specs)))
+    eng.close()
+    torch.cuda.empty_cache()
+    return {"boxes": len(specs), "cells": cells, "spheres": int(sum(s.n_particles for s in specs)),
+            "steps": steps, "mlups": cells * steps / dt / 1e6, "ms_per_step": dt * 1e3 / steps,
+            "storage": "f32dev", "launch": list(shape), "graph_steps": 10, "finite": bool(mass_ok),
+            "roofline_frac": cells * 152 / (dt / steps) / 1e9 / HBM_PEAK_GBPS}
+
+
+def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5):
+    """Moving dense suspension: every step the forces are read back, the
+    spheres advance by explicit Euler on the host (density ratio 2.5), are
+    uploaded, re-binned and re-mapped."""
+    import numpy as np
+
+    spec = inputs.dense_moving(n=n, seed=4)
+    eng = psm.Engine([psm.desc_from_spec(spec, max_radius=8.0)], storage=psm.PSM_FP32DEV)
+    with torch.cuda.stream(eng.stream):
+        u0 = torch.zeros((3, spec.N), dtype=torch.float64, device=eng.device)
+    eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+    eng.set_equilibrium(0, u0)
+    shape, _ = eng.autotune(trial_steps=3)
+    eng.set_equilibrium(0, u0)
+    del u0
+    x, U, Om = spec.x.copy(), spec.U.copy(), spec.Om.copy()
+    mass = 2.5 * 4.0 / 3.0 * np.pi * spec.r ** 3
+    inertia = 0.4 * mass * spec.r ** 2
+    L = np.asarray(spec.dims, dtype=np.float64)
+
+    def one():
+        nonlocal x, U, Om
+        eng.set_particles(0, x, spec.r, U, Om)
+        eng.step(1)
+        F, T = eng.get_forces(0)
+        x = np.mod(x + U, L)
+        U = U + F / mass[:, None]
+        Om = Om + T / inertia[:, None]
+
+    for _ in range(warmup):
+        one()
+    eng.reset_timing()
+    eng.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    dt = time.perf_counter() - t0
+    nl, kms = eng.get_timing()
+    _, _, ov = eng.get_stats(0)
+    eng.close()
+    torch.cuda.empty_cache()
+    step_ms = dt * 1e3 / steps
+    kern = kms / max(nl, 1)
+    return {"cells": spec.N, "spheres": int(len(spec.r)), "steps": steps, "storage": "f32dev",
+            "mlups": spec.N * steps / dt / 1e6, "ms_per_step": step_ms, "kernel_ms": kern,
+            "coupling_overhead_frac": (step_ms - kern) / step_ms, "launch": list(shape),
+            "slot_overflows_last_map": ov}
+
+
 def cpu_baseline(inputs, n, steps):
     import numpy as np
     import oracle
@@ -172,7 +254,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--launch", type=str, default=None, help="tx,ty,tz (skips the autotuner)")
+    ap.add_argument("--launch", type=str, default=None, help="tx,ty,tz,persistent (skips the autotuner)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--kernel-only", action="store_true", help="time psm_step alone (no upload/readback)")
     ap.add_argument("--precision-steps", type=int, default=200)
@@ -180,6 +262,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-size", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--batched-steps", type=int, default=500)
+    ap.add_argument("--dense-steps", type=int, default=200)
+    ap.add_argument("--dense-size", type=int, default=768)
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and dense workloads")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -223,6 +309,15 @@ def main():
         for k, v in err.items():
             forms[k]["error_vs_f64_64cubed_1000steps"] = v
         log(f"  {err}")
+
+    extra = {}
+    if not args.no_extra:
+        log("batched boxes")
+        extra["batched"] = run_batched(psm, torch, inputs, steps=args.batched_steps)
+        log(f"  {extra['batched']}")
+        log("dense moving spheres")
+        extra["dense_moving"] = run_dense_moving(psm, torch, inputs, n=args.dense_size, steps=args.dense_steps)
+        log(f"  {extra['dense_moving']}")
 
     log("stream copy")
     copy_gbps = stream_copy_gbps(psm, torch)
@@ -270,6 +365,7 @@ def main():
         "stream_copy_GBps": round(copy_gbps, 1),
         "mlups_frac_of_stream_copy": round(main_res["mlups"] * 1e6 * BYTES_PER_CELL[0] / 1e9 / copy_gbps, 4),
         "precision_forms": forms,
+        "other_workloads": extra,
     }
     print(json.dumps(out), flush=True)
 

@@ -5,7 +5,7 @@
  * fluid-particle simulations on heterogeneous CPU-GPU architectures"
  * (arXiv 2303.11811).
  *
- * One time step (Sec. 3.1 of the paper; Fig. 4 of its GPU time loop):
+ * One time step (Sec. 3.1 of the paper, the GPU part of its time loop):
  *   sphere -> cell solid-fraction mapping (Sec. 2.3.2, eqs. 25-27),
  *   D3Q19 SRT stream-collide with PSM coupling (Sec. 2.1 eqs. 1-8,
  *   Sec. 2.3 eqs. 17-20), and the per-particle hydrodynamic force and
@@ -120,7 +120,7 @@ int psm_set_particles(psm_ctx* ctx, int box, int n, const double* x, const doubl
                       const double* U, const double* omega);
 
 /* Advance every box by nsteps time steps: per step, fused mapping +
- * stream-collide + force/torque partial sums (one persistent launch over all
+ * stream-collide + force/torque partial sums (one launch over the tiles of all
  * boxes) and the per-particle reduction. With graphs enabled, runs of 10 steps
  * replay a captured HIP graph. Asynchronous. */
 int psm_step(psm_ctx* ctx, int nsteps);
@@ -143,16 +143,21 @@ int psm_get_solid_fraction(psm_ctx* ctx, int box, double* B, int* pid);
 int psm_get_stats(psm_ctx* ctx, int box, double* mass, double* momentum, long long* slot_overflows);
 
 /* Launch shape of the step kernel: a tile of tx*ty threads (tx*ty == 256,
- * tx in {16,32,64,128,256}) handling tz cells each along z. Rebuilds the tile
- * lists (synchronises); invalidates captured graphs. */
-int psm_set_launch(psm_ctx* ctx, int tx, int ty, int tz);
-int psm_get_launch(psm_ctx* ctx, int* tx, int* ty, int* tz);
+ * tx in {16,32,64,128,256}) handling tz cells each along z (tz in
+ * {1,2,4,8,16,32}); persistent = 1 sizes the grid to the workgroups that fit
+ * on the chip at once, each walking a contiguous share of the tiles, 0
+ * launches one workgroup per tile. Rebuilds the tile lists (synchronises);
+ * invalidates captured graphs. On failure the previous shape is restored.
+ * psm_get_launch: host outputs (persistent may be NULL). */
+int psm_set_launch(psm_ctx* ctx, int tx, int ty, int tz, int persistent);
+int psm_get_launch(psm_ctx* ctx, int* tx, int* ty, int* tz, int* persistent);
 
-/* Time every allowed launch shape on this context with HIP events
- * (warmup + trial_steps steps each), keep the fastest and report it.
- * The trial steps advance and overwrite the PDF state: set the state after
- * tuning. Synchronises. best_ms: host, ms per step of the chosen shape. */
-int psm_autotune(psm_ctx* ctx, int trial_steps, int* tx, int* ty, int* tz, double* best_ms);
+/* Time every allowed launch shape and grid mode on this context with HIP
+ * events (warmup + trial_steps steps each), keep the fastest and report it
+ * (host outputs, each may be NULL). The trial steps advance and overwrite
+ * the PDF state: set the state after tuning. Synchronises. best_ms: ms per
+ * step of the chosen launch. */
+int psm_autotune(psm_ctx* ctx, int trial_steps, int* tx, int* ty, int* tz, int* persistent, double* best_ms);
 
 /* Enable (1) / disable (0) HIP-graph replay of 10-step sequences in psm_step. */
 int psm_set_graph(psm_ctx* ctx, int enable);
@@ -166,8 +171,9 @@ int psm_get_timing(psm_ctx* ctx, long long* launches, double* total_ms);
 int psm_reset_timing(psm_ctx* ctx);
 
 /* Bandwidth reference (the paper's SCALE/STREAM measurement, Sec. 4): copy
- * `bytes` (multiple of 16) from src to dst (device, 16-byte aligned, not
- * overlapping) on hip_stream with a plain streaming copy kernel. */
+ * `bytes` (multiple of 16, at most 2^31 * 8 KiB) from src to dst (device,
+ * 16-byte aligned, not overlapping) on hip_stream with a plain one-shot
+ * streaming copy kernel. */
 int psm_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
 
 /* Text of the last error on this thread ("" if none). Never NULL. */

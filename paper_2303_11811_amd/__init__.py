@@ -56,11 +56,11 @@ _SIGS = {
     "psm_get_forces": ([_P, ctypes.c_int, _D, _D], ctypes.c_int),
     "psm_get_solid_fraction": ([_P, ctypes.c_int, _P, _P], ctypes.c_int),
     "psm_get_stats": ([_P, ctypes.c_int, _D, _D, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
-    "psm_set_launch": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "psm_set_launch": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "psm_get_launch": ([_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                        ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "psm_autotune": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                      ctypes.POINTER(ctypes.c_int), _D], ctypes.c_int),
+                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _D], ctypes.c_int),
     "psm_set_graph": ([_P, ctypes.c_int], ctypes.c_int),
     "psm_set_timing": ([_P, ctypes.c_int], ctypes.c_int),
     "psm_get_timing": ([_P, ctypes.POINTER(ctypes.c_longlong), _D], ctypes.c_int),
@@ -193,22 +193,22 @@ def psm_get_stats(ctx, box):
     return mass.value, mom, int(ov.value)
 
 
-def psm_set_launch(ctx, tx, ty, tz):
-    return _check(lib().psm_set_launch(ctx, int(tx), int(ty), int(tz)))
+def psm_set_launch(ctx, tx, ty, tz, persistent=0):
+    return _check(lib().psm_set_launch(ctx, int(tx), int(ty), int(tz), int(persistent)))
 
 
 def psm_get_launch(ctx):
-    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    _check(lib().psm_get_launch(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-    return a.value, b.value, c.value
+    a, b, c, d = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().psm_get_launch(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+    return a.value, b.value, c.value, d.value
 
 
 def psm_autotune(ctx, trial_steps):
-    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    a, b, c, d = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     ms = ctypes.c_double()
     _check(lib().psm_autotune(ctx, int(trial_steps), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
-                              ctypes.byref(ms)))
-    return (a.value, b.value, c.value), ms.value
+                              ctypes.byref(d), ctypes.byref(ms)))
+    return (a.value, b.value, c.value, d.value), ms.value
 
 
 def psm_set_graph(ctx, enable):
@@ -348,8 +348,8 @@ class Engine:
     def get_stats(self, box=0):
         return psm_get_stats(self.ctx, box)
 
-    def set_launch(self, tx, ty, tz):
-        psm_set_launch(self.ctx, tx, ty, tz)
+    def set_launch(self, tx, ty, tz, persistent=0):
+        psm_set_launch(self.ctx, tx, ty, tz, persistent)
 
     def get_launch(self):
         return psm_get_launch(self.ctx)

@@ -73,7 +73,7 @@ static int max_tiles_axis(double rmax, int T, int L) {
 
 struct Layout {
     size_t off_boxes, off_tbase, off_partbox, off_pt, off_acc, off_tcnt, off_toff, off_tpid, off_partial,
-        off_misc, off_statpart, total;
+        off_misc, off_statpart, off_scan, total;
     std::vector<size_t> off_grid[2];
     std::vector<long long> qstride;
     int T_max;
@@ -156,6 +156,7 @@ static Layout make_layout(const psm_box_desc* boxes, int nbox, int storage) {
     L.off_partial = take(sizeof(double) * 6 * (size_t)L.cap_max);
     L.off_misc = take(256);
     L.off_statpart = take(sizeof(double) * 4 * (size_t)stats_blocks() + 64);
+    L.off_scan = take(sizeof(int) * 2 * (size_t)scan_chunks(Tmax) + 64);
     for (int p = 0; p < 2; ++p) L.off_grid[p].resize(nbox);
     L.qstride.resize(nbox);
     for (int b = 0; b < nbox; ++b) {
@@ -182,7 +183,7 @@ struct psm_ctx {
     std::vector<BoxDev> box;     // host copy of the device box table
     std::vector<int> np;         // particles set per box
     int P_total = 0;
-    TileShape ts{64, 4, 16};
+    TileShape ts{64, 4, 16, 0};
     int T_total = 0;
     int grid = 0;
     int parity = 0;
@@ -196,6 +197,9 @@ struct psm_ctx {
     double* d_partial = nullptr;
     int* d_misc = nullptr;               // [0..1] bin stats, [8..9] dropped (u64)
     double* d_statpart = nullptr;
+    int* d_scan = nullptr;               // scan scratch (chunk sums and maxima)
+    // last uploaded positions and radii per box: unchanged geometry keeps the lists
+    std::vector<std::vector<double>> last_xr;
     // pinned host staging
     double* h_stage = nullptr;
     size_t h_stage_n = 0;
@@ -244,8 +248,10 @@ static void assign_tiles(psm_ctx* c) {
     int dev = 0, ncu = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    int g = step_blocks_per_cu(c->storage, c->map_mode) * ncu;
-    g = std::min(g, ((c->T_total + NXCD - 1) / NXCD) * NXCD);
+    // one-shot: a workgroup per tile (rounded up to whole XCD rounds);
+    // persistent: as many workgroups as fit at once, each walking its tiles
+    int full = ((c->T_total + NXCD - 1) / NXCD) * NXCD;
+    int g = c->ts.persistent ? std::min(step_blocks_per_cu(c->storage, c->map_mode) * ncu, full) : full;
     c->grid = std::max(NXCD, g / NXCD * NXCD);
 }
 
@@ -263,7 +269,7 @@ static int rebuild_lists(psm_ctx* c) {
     bp.P_total = c->P_total;
     bp.T_total = c->T_total;
     bp.ts = c->ts;
-    HIP_TRY(launch_bin(bp, c->d_misc, c->stream));
+    HIP_TRY(launch_bin(bp, c->d_misc, c->d_scan, c->stream));
     int stats[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(stats, c->d_misc, sizeof stats, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -369,6 +375,8 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
     c->d_partial = (double*)(c->ws + L.off_partial);
     c->d_misc = (int*)(c->ws + L.off_misc);
     c->d_statpart = (double*)(c->ws + L.off_statpart);
+    c->d_scan = (int*)(c->ws + L.off_scan);
+    c->last_xr.assign(nbox, std::vector<double>());
 
     int err = PSM_OK;
     auto hip_ok = [&](hipError_t e, const char* what) {
@@ -513,11 +521,22 @@ extern "C" int psm_set_particles(psm_ctx* c, int box, int n, const double* x, co
         for (int k = 0; k < 11; ++k)
             HIP_TRY(hipMemcpyAsync(cols[k] + pb, st + (size_t)k * m, sizeof(double) * n, hipMemcpyHostToDevice,
                                    c->stream));
+    // positions (wrapped) and radii decide the tile lists; velocities do not
+    std::vector<double> xr((size_t)4 * n);
+    std::memcpy(xr.data(), st, sizeof(double) * n);
+    std::memcpy(xr.data() + n, st + m, sizeof(double) * n);
+    std::memcpy(xr.data() + 2 * n, st + 2 * m, sizeof(double) * n);
+    std::memcpy(xr.data() + 3 * n, st + 3 * m, sizeof(double) * n);
+    bool same_geometry = c->have_particles_lists && c->np[box] == n && xr == c->last_xr[box];
     c->box[box].np = n;
     c->np[box] = n;
     HIP_TRY(hipMemcpyAsync(&c->d_boxes[box].np, &c->box[box].np, sizeof(int), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));   // staging is reused by the next call
-    return rebuild_lists(c);
+    if (same_geometry) return PSM_OK;
+    c->last_xr[box].swap(xr);
+    rc = rebuild_lists(c);
+    if (rc != PSM_OK) c->last_xr[box].clear();
+    return rc;
 }
 
 static int step_params(psm_ctx* c, int parity, StepParams& kp) {
@@ -669,12 +688,13 @@ extern "C" int psm_get_stats(psm_ctx* c, int box, double* mass, double* momentum
     return PSM_OK;
 }
 
-extern "C" int psm_set_launch(psm_ctx* c, int tx, int ty, int tz) {
+extern "C" int psm_set_launch(psm_ctx* c, int tx, int ty, int tz, int persistent) {
     if (!c) return fail(PSM_EINVAL, "ctx is NULL");
     if (!shape_allowed(tx, ty, tz)) return fail(PSM_EINVAL, "launch shape %dx%dx%d not allowed", tx, ty, tz);
+    if (persistent != 0 && persistent != 1) return fail(PSM_EINVAL, "persistent must be 0 or 1");
     HIP_TRY(hipStreamSynchronize(c->stream));
     TileShape old = c->ts;
-    c->ts = TileShape{tx, ty, tz};
+    c->ts = TileShape{tx, ty, tz, persistent};
     assign_tiles(c);
     int rc = upload_box_table(c);
     if (rc == PSM_OK) rc = rebuild_lists(c);
@@ -682,7 +702,7 @@ extern "C" int psm_set_launch(psm_ctx* c, int tx, int ty, int tz) {
         std::string msg = g_err;
         c->ts = old;
         assign_tiles(c);
-        if (upload_box_table(c) == PSM_OK) rebuild_lists(c);
+        if (upload_box_table(c) == PSM_OK) (void)rebuild_lists(c);
         g_err = msg;
         return rc;
     }
@@ -690,9 +710,10 @@ extern "C" int psm_set_launch(psm_ctx* c, int tx, int ty, int tz) {
     return PSM_OK;
 }
 
-extern "C" int psm_get_launch(psm_ctx* c, int* tx, int* ty, int* tz) {
+extern "C" int psm_get_launch(psm_ctx* c, int* tx, int* ty, int* tz, int* persistent) {
     if (!c || !tx || !ty || !tz) return fail(PSM_EINVAL, "NULL argument");
     *tx = c->ts.tx; *ty = c->ts.ty; *tz = c->ts.tz;
+    if (persistent) *persistent = c->ts.persistent;
     return PSM_OK;
 }
 
@@ -733,7 +754,8 @@ extern "C" int psm_reset_timing(psm_ctx* c) {
     return PSM_OK;
 }
 
-extern "C" int psm_autotune(psm_ctx* c, int trial_steps, int* tx, int* ty, int* tz, double* best_ms) {
+extern "C" int psm_autotune(psm_ctx* c, int trial_steps, int* tx, int* ty, int* tz, int* persistent,
+                            double* best_ms) {
     if (!c) return fail(PSM_EINVAL, "ctx is NULL");
     if (trial_steps < 1) return fail(PSM_EINVAL, "trial_steps must be >= 1");
     TileShape best = c->ts;
@@ -746,12 +768,13 @@ extern "C" int psm_autotune(psm_ctx* c, int trial_steps, int* tx, int* ty, int* 
     HIP_TRY(hipEventCreate(&e1));
     int maxdim = 0;
     for (auto& d : c->desc) maxdim = std::max(maxdim, d.nx);
+    for (int pers = 0; pers < 2; ++pers)
     for (int txv : kTX) {
         // tiles much wider than the widest box only idle lanes
         if (txv > 2 * std::max(maxdim, 16)) continue;
         for (int tzv : kTZ) {
             int tyv = WG / txv;
-            if (psm_set_launch(c, txv, tyv, tzv) != PSM_OK) continue;
+            if (psm_set_launch(c, txv, tyv, tzv, pers) != PSM_OK) continue;
             int rc = psm_step(c, 2);
             if (rc) break;
             (void)hipEventRecord(e0, c->stream);
@@ -772,11 +795,12 @@ extern "C" int psm_autotune(psm_ctx* c, int trial_steps, int* tx, int* ty, int* 
     (void)hipEventDestroy(e1);
     c->timing = was_timing;
     c->use_graph = was_graph;
-    int rc = psm_set_launch(c, best.tx, best.ty, best.tz);
+    int rc = psm_set_launch(c, best.tx, best.ty, best.tz, best.persistent);
     if (rc) return rc;
     if (tx) *tx = best.tx;
     if (ty) *ty = best.ty;
     if (tz) *tz = best.tz;
+    if (persistent) *persistent = best.persistent;
     if (best_ms) *best_ms = best_t;
     return PSM_OK;
 }

@@ -50,6 +50,7 @@ struct Particles {
 
 struct TileShape {
     int tx, ty, tz;
+    int persistent;   // 1: occupancy-sized grid walking the tiles; 0: one workgroup per tile
 };
 
 // ---------------------------------------------------------------------------
@@ -233,7 +234,8 @@ struct BinParams {
 hipError_t launch_step(int storage, int map, const StepParams& kp, int grid, hipStream_t st);
 int step_blocks_per_cu(int storage, int map);
 hipError_t launch_reduce(const ReduceParams& rp, hipStream_t st);
-hipError_t launch_bin(const BinParams& bp, int* stats, hipStream_t st);
+int scan_chunks(int n);
+hipError_t launch_bin(const BinParams& bp, int* stats, int* scratch, hipStream_t st);
 hipError_t launch_bin_fill(const BinParams& bp, hipStream_t st);
 hipError_t launch_set_pdfs(int storage, const BoxDev& bx, int parity, const double* f, float scale, hipStream_t st);
 hipError_t launch_set_equilibrium(int storage, const BoxDev& bx, int parity, const double* rho, const double* u,

@@ -21,6 +21,29 @@ namespace psm {
 #define GLOBAL __attribute__((address_space(1)))
 typedef const GLOBAL char GCHAR;
 
+// Cache policy of the PDF streams (compile-time switches, measured by the
+// autotuning sweeps): nontemporal stores / loads bypass cache retention.
+#ifndef PSM_NT_STORE
+#define PSM_NT_STORE 1
+#endif
+#ifndef PSM_NT_LOAD
+#define PSM_NT_LOAD 0
+#endif
+template <class T> __device__ __forceinline__ T ld_pdf(const GLOBAL T* p) {
+#if PSM_NT_LOAD
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+template <class T> __device__ __forceinline__ void st_pdf(GLOBAL T* p, T v) {
+#if PSM_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
 // ---------------------------------------------------------------------------
 // Storage traits: FP64 stores f; the deviation forms store d = f - w_q
 // (FP16 as scale * d) and compute in FP32.
@@ -28,8 +51,8 @@ struct St64 {
     using T = double;
     using R = double;
     static constexpr bool DEV = false;
-    __device__ static R loadb(const GCHAR* b, unsigned off, float) { return *(const GLOBAL T*)(b + off); }
-    __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float) { *(GLOBAL T*)(b + off) = v; }
+    __device__ static R loadb(const GCHAR* b, unsigned off, float) { return ld_pdf((const GLOBAL T*)(b + off)); }
+    __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float) { st_pdf((GLOBAL T*)(b + off), v); }
     __device__ static double to_f64(T v, float) { return v; }
     __device__ static T from_f64(double v, float) { return v; }
 };
@@ -37,8 +60,8 @@ struct St32 {
     using T = float;
     using R = float;
     static constexpr bool DEV = true;
-    __device__ static R loadb(const GCHAR* b, unsigned off, float) { return *(const GLOBAL T*)(b + off); }
-    __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float) { *(GLOBAL T*)(b + off) = v; }
+    __device__ static R loadb(const GCHAR* b, unsigned off, float) { return ld_pdf((const GLOBAL T*)(b + off)); }
+    __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float) { st_pdf((GLOBAL T*)(b + off), v); }
     __device__ static double to_f64(T v, float) { return (double)v; }
     __device__ static T from_f64(double v, float) { return (float)v; }
 };
@@ -47,9 +70,11 @@ struct St16 {
     using R = float;
     static constexpr bool DEV = true;
     // scale is a power of two: multiplication by it and by 1/scale is exact
-    __device__ static R loadb(const GCHAR* b, unsigned off, float inv) { return (float)*(const GLOBAL T*)(b + off) * inv; }
+    __device__ static R loadb(const GCHAR* b, unsigned off, float inv) {
+        return (float)ld_pdf((const GLOBAL T*)(b + off)) * inv;
+    }
     __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float scale) {
-        *(GLOBAL T*)(b + off) = (_Float16)(v * scale);
+        st_pdf((GLOBAL T*)(b + off), (_Float16)(v * scale));
     }
     __device__ static double to_f64(T v, float inv) { return (double)((float)v * inv); }
     __device__ static T from_f64(double v, float scale) { return (_Float16)(float)(v * (double)scale); }
@@ -291,12 +316,17 @@ __global__ __launch_bounds__(WG) void k_psm_step(StepParams kp) {
                 R Ug3 = (R)3.0 * (Ux * gx + Uy * gy + Uz * gz);
                 const R pu0 = (R)bx.pw[0] * Ug3, pu1 = (R)bx.pw[1] * Ug3, pu2 = (R)bx.pw[2] * Ug3;
 
-                // 4. collision
+                // 4. collision; each pair is stored as soon as it is final
+                const unsigned ob = (unsigned)(xs + r00) * (unsigned)sizeof(T);
+#define PSM_STORE(Q) S::storeb(db + (Q) * qsb, ob, f[Q], kp.h_scale)
                 if (!psm_wave) {
                     f[0] = f[0] + (omega * ((R)W0 * base - f[0]) - pu0);
+                    PSM_STORE(0);
 #define PSM_PAIR(Q)                                                                                           \
     pair_fluid<R, Q>(f[Q], f[Q + 1], base, Ux, Uy, Uz, (R)bx.fa[Q / 2], (R)bx.fs[Q / 2], Q < 7 ? pu1 : pu2, \
-                     omega)
+                     omega);                                                                                  \
+    PSM_STORE(Q);                                                                                             \
+    PSM_STORE(Q + 1)
                     PSM_PAIR(1); PSM_PAIR(3); PSM_PAIR(5); PSM_PAIR(7); PSM_PAIR(9);
                     PSM_PAIR(11); PSM_PAIR(13); PSM_PAIR(15); PSM_PAIR(17);
 #undef PSM_PAIR
@@ -333,18 +363,18 @@ __global__ __launch_bounds__(WG) void k_psm_step(StepParams kp) {
                         R s0 = w * base;
                         R t0 = omega * (s0 - f[0]) - pu0;
                         f[0] = (f[0] + omB * t0) + (w * A0 - Bt * s0);
+                        PSM_STORE(0);
                     }
 #define PSM_PAIR(Q)                                                                                       \
     pair_psm<R, Q>(f[Q], f[Q + 1], base, Ux, Uy, Uz, (R)bx.fa[Q / 2], (R)bx.fs[Q / 2], Q < 7 ? pu1 : pu2, omega, \
-                   Bt, omB, A0, Mxx, Myy, Mzz, Mxy, Mxz, Myz, Px, Py, Pz)
+                   Bt, omB, A0, Mxx, Myy, Mzz, Mxy, Mxz, Myz, Px, Py, Pz);                                       \
+    PSM_STORE(Q);                                                                                                \
+    PSM_STORE(Q + 1)
                     PSM_PAIR(1); PSM_PAIR(3); PSM_PAIR(5); PSM_PAIR(7); PSM_PAIR(9);
                     PSM_PAIR(11); PSM_PAIR(13); PSM_PAIR(15); PSM_PAIR(17);
 #undef PSM_PAIR
                 }
-                const long long n = xs + r00;
-#pragma unroll
-                for (int q = 0; q < NQ; ++q)
-                    S::storeb(db + q * qsb, (unsigned)n * (unsigned)sizeof(T), f[q], kp.h_scale);
+#undef PSM_STORE
             }
 
             // 5. force and torque of eqs. (21)-(22): sum_q C^solid_{q,s} c_qbar
@@ -400,10 +430,13 @@ __global__ __launch_bounds__(WG) void k_psm_step(StepParams kp) {
 // ---------------------------------------------------------------------------
 // Per-sphere force/torque: sum the tile partials of every tile of the
 // sphere's bounding box, in a fixed tile order (deterministic).
-__global__ void k_reduce_forces(ReduceParams rp) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= rp.P_total) return;
-    int b = rp.part_box[p];
+// One 64-wide wave per sphere: lane l takes the sphere's tiles l, l+64, ...
+// (in the fixed bounding-box order), then a fixed butterfly adds the lanes.
+__global__ __launch_bounds__(256) void k_reduce_forces(ReduceParams rp) {
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= rp.P_total) return;   // whole wave leaves together
+    const int b = rp.part_box[p];
     const BoxDev& bx = rp.boxes[b];
     double acc[6] = {0, 0, 0, 0, 0, 0};
     if (p - bx.part_base < bx.np) {
@@ -414,30 +447,36 @@ __global__ void k_reduce_forces(ReduceParams rp) {
         AxisTiles ay = axis_tiles(lo, hi, bx.ny, rp.ts.ty, bx.nty);
         aabb_cells(rp.P.z[p], rp.P.r[p], lo, hi);
         AxisTiles az = axis_tiles(lo, hi, bx.nz, rp.ts.tz, bx.ntz);
-        int nzt = az.count(), nyt = ay.count(), nxt = ax.count();
-        for (int kz = 0; kz < nzt; ++kz)
-            for (int ky = 0; ky < nyt; ++ky)
-                for (int kx = 0; kx < nxt; ++kx) {
-                    int t = bx.tile_base + ax.at(kx) + bx.ntx * (ay.at(ky) + bx.nty * az.at(kz));
-                    int e0 = rp.tile_off[t], e1 = rp.tile_off[t + 1];
-                    for (int e = e0; e < e1; ++e)
-                        if (rp.tile_pid[e] == p) {
-                            for (int k = 0; k < 6; ++k) acc[k] += rp.partial[(long long)e * 6 + k];
-                            break;
-                        }
+        const int nxt = ax.count(), nyt = ay.count(), nzt = az.count();
+        const int ntot = nxt * nyt * nzt;
+        for (int k = lane; k < ntot; k += 64) {
+            int kx = k % nxt, ky = (k / nxt) % nyt, kz = k / (nxt * nyt);
+            int t = bx.tile_base + ax.at(kx) + bx.ntx * (ay.at(ky) + bx.nty * az.at(kz));
+            int e0 = rp.tile_off[t], e1 = rp.tile_off[t + 1];
+            for (int e = e0; e < e1; ++e)
+                if (rp.tile_pid[e] == p) {
+                    for (int c = 0; c < 6; ++c) acc[c] += rp.partial[(long long)e * 6 + c];
+                    break;
                 }
+        }
     }
-    for (int k = 0; k < 6; ++k) rp.P.acc[(long long)p * 6 + k] = acc[k];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        double v = wave_sum(acc[c]);
+        if (lane == 0) rp.P.acc[(long long)p * 6 + c] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Tile binning (the paper's sub-block particle lists, built on the device):
 // count -> exclusive scan -> fill.
+// One 64-wide wave per sphere; its lanes walk the bounding box's tiles.
 template <bool FILL>
-__global__ void k_bin(BinParams bp) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_bin(BinParams bp) {
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (p >= bp.P_total) return;
-    int b = bp.part_box[p];
+    const int b = bp.part_box[p];
     const BoxDev& bx = bp.boxes[b];
     if (p - bx.part_base >= bx.np) return;
     int lo, hi;
@@ -447,18 +486,18 @@ __global__ void k_bin(BinParams bp) {
     AxisTiles ay = axis_tiles(lo, hi, bx.ny, bp.ts.ty, bx.nty);
     aabb_cells(bp.P.z[p], bp.P.r[p], lo, hi);
     AxisTiles az = axis_tiles(lo, hi, bx.nz, bp.ts.tz, bx.ntz);
-    int nzt = az.count(), nyt = ay.count(), nxt = ax.count();
-    for (int kz = 0; kz < nzt; ++kz)
-        for (int ky = 0; ky < nyt; ++ky)
-            for (int kx = 0; kx < nxt; ++kx) {
-                int t = bx.tile_base + ax.at(kx) + bx.ntx * (ay.at(ky) + bx.nty * az.at(kz));
-                if (!FILL) {
-                    atomicAdd(&bp.tile_cnt[t], 1);
-                } else {
-                    int pos = atomicSub(&bp.tile_cnt[t], 1) - 1;
-                    bp.tile_pid[bp.tile_off[t] + pos] = p;
-                }
-            }
+    const int nxt = ax.count(), nyt = ay.count(), nzt = az.count();
+    const int ntot = nxt * nyt * nzt;
+    for (int k = lane; k < ntot; k += 64) {
+        int kx = k % nxt, ky = (k / nxt) % nyt, kz = k / (nxt * nyt);
+        int t = bx.tile_base + ax.at(kx) + bx.ntx * (ay.at(ky) + bx.nty * az.at(kz));
+        if (!FILL) {
+            atomicAdd(&bp.tile_cnt[t], 1);
+        } else {
+            int pos = atomicSub(&bp.tile_cnt[t], 1) - 1;
+            bp.tile_pid[bp.tile_off[t] + pos] = p;
+        }
+    }
 }
 
 __global__ void k_fill_int(int* a, long long n, int v) {
@@ -467,48 +506,99 @@ __global__ void k_fill_int(int* a, long long n, int v) {
     for (; i < n; i += stride) a[i] = v;
 }
 
-// Exclusive scan of cnt[0..n) into off[0..n]; one workgroup of 1024 threads.
-// stats[0] = largest count, stats[1] = total.
-__global__ __launch_bounds__(1024) void k_scan(const int* cnt, int* off, int n, int* stats) {
-    __shared__ int s_part[1024];
+// Exclusive scan of cnt[0..n) into off[0..n] in three passes over chunks of
+// SCAN_CHUNK counts: chunk sums and maxima, a one-workgroup scan of the chunk
+// sums, then each chunk scanned with its offset. stats[0] = largest count,
+// stats[1] = total.
+constexpr int SCAN_CHUNK = 1024;
+
+__device__ inline int block_incl_scan_256(int v, int* sh) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        int add = tid >= d ? sh[tid - d] : 0;
+        __syncthreads();
+        sh[tid] += add;
+        __syncthreads();
+    }
+    int r = sh[tid];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_scan_chunks(const int* cnt, int n, int* csum, int* cmax) {
+    __shared__ int s_sum[256], s_max[256];
+    const int tid = threadIdx.x;
+    const int base = blockIdx.x * SCAN_CHUNK;
+    int sum = 0, mx = 0;
+    for (int k = 0; k < SCAN_CHUNK / 256; ++k) {
+        int i = base + k * 256 + tid;
+        int v = i < n ? cnt[i] : 0;
+        sum += v;
+        mx = v > mx ? v : mx;
+    }
+    s_sum[tid] = sum;
+    s_max[tid] = mx;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if (tid < d) {
+            s_sum[tid] += s_sum[tid + d];
+            s_max[tid] = s_max[tid] > s_max[tid + d] ? s_max[tid] : s_max[tid + d];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        csum[blockIdx.x] = s_sum[0];
+        cmax[blockIdx.x] = s_max[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums(int* csum, const int* cmax, int nchunk, int* stats) {
+    __shared__ int sh[256];
     __shared__ int s_carry, s_max;
     const int tid = threadIdx.x;
     if (tid == 0) { s_carry = 0; s_max = 0; }
     __syncthreads();
     int mymax = 0;
-    for (int base = 0; base < n; base += 1024 * 4) {
-        int v[4], loc = 0;
-        for (int k = 0; k < 4; ++k) {
-            int i = base + tid * 4 + k;
-            v[k] = i < n ? cnt[i] : 0;
-            mymax = v[k] > mymax ? v[k] : mymax;
-            loc += v[k];
-        }
-        s_part[tid] = loc;
+    for (int base = 0; base < nchunk; base += 256) {
+        int i = base + tid;
+        int v = i < nchunk ? csum[i] : 0;
+        mymax = (i < nchunk && cmax[i] > mymax) ? cmax[i] : mymax;
+        int inc = block_incl_scan_256(v, sh);
+        if (i < nchunk) csum[i] = s_carry + inc - v;   // exclusive offset of chunk i
         __syncthreads();
-        for (int d = 1; d < 1024; d <<= 1) {
-            int add = tid >= d ? s_part[tid - d] : 0;
-            __syncthreads();
-            s_part[tid] += add;
-            __syncthreads();
-        }
-        int run = s_carry + (s_part[tid] - loc);
-        for (int k = 0; k < 4; ++k) {
-            int i = base + tid * 4 + k;
-            if (i < n) off[i] = run;
-            run += v[k];
-        }
-        __syncthreads();
-        if (tid == 1023) s_carry += s_part[1023];
+        if (tid == 255) s_carry += inc;
         __syncthreads();
     }
     atomicMax(&s_max, mymax);
     __syncthreads();
     if (tid == 0) {
-        off[n] = s_carry;
         stats[0] = s_max;
         stats[1] = s_carry;
     }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const int* cnt, int n, const int* coff, int* off,
+                                                    const int* stats) {
+    __shared__ int sh[256];
+    const int tid = threadIdx.x;
+    const int base = blockIdx.x * SCAN_CHUNK;
+    // each thread owns 4 consecutive counts
+    int v[4], loc = 0;
+    for (int k = 0; k < 4; ++k) {
+        int i = base + tid * 4 + k;
+        v[k] = i < n ? cnt[i] : 0;
+        loc += v[k];
+    }
+    int inc = block_incl_scan_256(loc, sh);
+    int run = coff[blockIdx.x] + inc - loc;
+    for (int k = 0; k < 4; ++k) {
+        int i = base + tid * 4 + k;
+        if (i < n) off[i] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && tid == 0) off[n] = stats[1];
 }
 
 // ---------------------------------------------------------------------------
@@ -687,12 +777,17 @@ __global__ void k_stats_final(const double* part, int nblk, double* out) {
     }
 }
 
-// Plain streaming copy (bandwidth reference).
+// Plain streaming copy (bandwidth reference): one-shot grid, each thread
+// moves two 16-byte vectors (loads first, then stores).
 __global__ __launch_bounds__(256) void k_stream_copy(const double2* __restrict__ a, double2* __restrict__ b,
                                                      long long n) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long stride = (long long)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) b[i] = a[i];
+    long long i0 = (long long)blockIdx.x * 512 + threadIdx.x;
+    long long i1 = i0 + 256;
+    double2 v0, v1;
+    if (i0 < n) v0 = a[i0];
+    if (i1 < n) v1 = a[i1];
+    if (i0 < n) b[i0] = v0;
+    if (i1 < n) b[i1] = v1;
 }
 
 // ---------------------------------------------------------------------------
@@ -732,22 +827,31 @@ int step_blocks_per_cu(int storage, int map) {
 
 hipError_t launch_reduce(const ReduceParams& rp, hipStream_t st) {
     if (rp.P_total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_forces, dim3(blocks_for(rp.P_total, 128)), dim3(128), 0, st, rp);
+    hipLaunchKernelGGL(k_reduce_forces, dim3(blocks_for(rp.P_total, 4)), dim3(256), 0, st, rp);
     return hipGetLastError();
 }
 
-hipError_t launch_bin(const BinParams& bp, int* stats, hipStream_t st) {
+int scan_chunks(int n) { return (n + SCAN_CHUNK - 1) / SCAN_CHUNK; }
+
+// scratch: 2 * scan_chunks(T) ints
+hipError_t launch_bin(const BinParams& bp, int* stats, int* scratch, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(bp.T_total, 256) > 4096 ? 4096 : blocks_for(bp.T_total, 256)),
                        dim3(256), 0, st, bp.tile_cnt, (long long)bp.T_total, 0);
     if (bp.P_total > 0)
-        hipLaunchKernelGGL(k_bin<false>, dim3(blocks_for(bp.P_total, 128)), dim3(128), 0, st, bp);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, bp.tile_cnt, bp.tile_off, bp.T_total, stats);
+        hipLaunchKernelGGL(k_bin<false>, dim3(blocks_for(bp.P_total, 4)), dim3(256), 0, st, bp);
+    int nch = scan_chunks(bp.T_total);
+    int* csum = scratch;
+    int* cmax = scratch + nch;
+    hipLaunchKernelGGL(k_scan_chunks, dim3(nch), dim3(256), 0, st, bp.tile_cnt, bp.T_total, csum, cmax);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, st, csum, cmax, nch, stats);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nch), dim3(256), 0, st, bp.tile_cnt, bp.T_total, csum, bp.tile_off,
+                       stats);
     return hipGetLastError();
 }
 
 hipError_t launch_bin_fill(const BinParams& bp, hipStream_t st) {
     if (bp.P_total > 0)
-        hipLaunchKernelGGL(k_bin<true>, dim3(blocks_for(bp.P_total, 128)), dim3(128), 0, st, bp);
+        hipLaunchKernelGGL(k_bin<true>, dim3(blocks_for(bp.P_total, 4)), dim3(256), 0, st, bp);
     return hipGetLastError();
 }
 
@@ -828,13 +932,11 @@ hipError_t launch_stats(int storage, const BoxDev& bx, int parity, float inv, do
 
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st) {
     long long n = (long long)(bytes / 16);
-    int dev = 0, ncu = 256;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    long long blocks = (n + 255) / 256;
-    long long cap = (long long)ncu * 16;
-    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)(blocks < cap ? blocks : cap)), dim3(256), 0, st,
-                       (const double2*)src, (double2*)dst, n);
+    long long blocks = (n + 511) / 512;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const double2*)src, (double2*)dst,
+                       n);
     return hipGetLastError();
 }
 

@@ -22,15 +22,66 @@ from dataclasses import dataclass, field
 import numpy as np
 
 
+def _rsa_equal(L, n, r, rng, gap, batch=512, max_candidates=None):
+    """Random sequential addition of n spheres of one radius r: candidates are
+    drawn in batches and taken in draw order, each accepted iff it keeps the
+    distance 2r + gap (minimum image) to every sphere accepted before it."""
+    dmin = 2.0 * r + gap
+    ng = np.maximum((L // dmin).astype(int), 1)
+    csz = L / ng
+    cap = int(np.prod(np.floor(csz / max(2.0 * r, 1.0)) + 1))
+    grid = -np.ones((ng[0], ng[1], ng[2], cap), dtype=np.int64)
+    fill = np.zeros((ng[0], ng[1], ng[2]), dtype=np.int64)
+    xs = np.zeros((n, 3))
+    offs = np.array([(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)])
+    count = 0
+    drawn = 0
+    max_candidates = max_candidates or 200 * n + 100000
+    while count < n and drawn < max_candidates:
+        cand = rng.random((batch, 3)) * L
+        drawn += batch
+        gc = np.minimum((cand // csz).astype(int), ng - 1)
+        # conflicts with spheres accepted in earlier batches
+        nb = (gc[:, None, :] + offs[None, :, :]) % ng
+        idx = grid[nb[..., 0], nb[..., 1], nb[..., 2]].reshape(batch, -1)
+        d = cand[:, None, :] - xs[np.maximum(idx, 0)]
+        d -= L * np.round(d / L)
+        close = ((d * d).sum(-1) < dmin * dmin) & (idx >= 0)
+        ok = ~close.any(axis=1)
+        # conflicts among the candidates of this batch, resolved in draw order
+        dd = cand[:, None, :] - cand[None, :, :]
+        dd -= L * np.round(dd / L)
+        pair = (dd * dd).sum(-1) < dmin * dmin
+        taken = []
+        for j in np.nonzero(ok)[0]:
+            if count >= n:
+                break
+            if taken and pair[j, taken].any():
+                continue
+            k = fill[gc[j, 0], gc[j, 1], gc[j, 2]]
+            if k >= cap:
+                continue
+            grid[gc[j, 0], gc[j, 1], gc[j, 2], k] = count
+            fill[gc[j, 0], gc[j, 1], gc[j, 2]] += 1
+            xs[count] = cand[j]
+            taken.append(j)
+            count += 1
+    return xs[:count].copy(), np.full(count, r)
+
+
 def rsa_spheres(dims, radii, rng, max_attempts_per_sphere=20000, gap=0.0):
     """Place spheres of the given radii one after another at uniform random
     centres in [0,L)^3, rejecting any candidate closer than r_i + r_j + gap
     (minimum image) to an accepted sphere. A sphere that finds no place within
-    ``max_attempts_per_sphere`` candidates is dropped. Returns (x (n,3), r (n,))."""
+    ``max_attempts_per_sphere`` candidates is dropped. Equal radii take the
+    batched path (same acceptance rule, candidates drawn 512 at a time).
+    Returns (x (n,3), r (n,))."""
     L = np.asarray(dims, dtype=np.float64)
     radii = np.asarray(radii, dtype=np.float64)
     if len(radii) == 0:
         return np.zeros((0, 3)), np.zeros(0)
+    if len(radii) > 64 and np.all(radii == radii[0]):
+        return _rsa_equal(L, len(radii), float(radii[0]), rng, gap)
     rmax = float(radii.max())
     cell = 2.0 * rmax + gap
     ng = np.maximum((L // cell).astype(int), 1)
@@ -74,6 +125,27 @@ def rsa_spheres(dims, radii, rng, max_attempts_per_sphere=20000, gap=0.0):
                 placed = True
                 break
     return xs[:n].copy(), rs[:n].copy()
+
+
+def jittered_lattice_spheres(dims, n, r, rng):
+    """n non-overlapping spheres of radius r for dense packings (where random
+    sequential addition slows down near jamming): the smallest cubic lattice
+    with at least n sites, a seeded choice of n sites, each centre jittered
+    uniformly by up to half the gap between neighbouring spheres per axis.
+    Needs a lattice spacing >= 2r."""
+    L = np.asarray(dims, dtype=np.float64)
+    m = int(math.ceil((n * np.prod(L) / L.min() ** 3) ** (1.0 / 3.0)))
+    counts = np.maximum((m * L / L.min()).astype(int), 1)
+    while np.prod(counts) < n:
+        counts[np.argmin(L / counts)] += 1
+    a = L / counts
+    if np.any(a < 2.0 * r):
+        raise ValueError("solid fraction too high for a jittered lattice")
+    sites = np.stack(np.meshgrid(*[np.arange(c) for c in counts], indexing="ij"), -1).reshape(-1, 3)
+    pick = rng.choice(len(sites), n, replace=False)
+    jit = (rng.random((n, 3)) * 2.0 - 1.0) * (a - 2.0 * r) / 2.0
+    x = np.mod((sites[pick] + 0.5) * a + jit, L)
+    return x, np.full(n, float(r))
 
 
 def uniform_velocities(rng, n, amp):
@@ -189,12 +261,12 @@ def batched_boxes(nbox=64, seed=3):
 
 def dense_moving(n=768, seed=4, phi=0.30, radius=8.0, vamp=0.005):
     """n^3 periodic box (768 at full size), fluid at rest, spheres of
-    diameter 16 at 30 % solid volume fraction (63,365 at 768^3), velocities
-    in [-0.005, 0.005]^3, tau 0.6, linear mapping."""
+    diameter 16 at 30 % solid volume fraction (63,365 at 768^3) on a seeded
+    jittered lattice, velocities in [-0.005, 0.005]^3, tau 0.6, linear mapping."""
     rng = np.random.default_rng(seed)
     dims = (n, n, n)
     np_ = n_spheres_for_fraction(dims, phi, radius)
-    x, r = rsa_spheres(dims, np.full(np_, radius), rng)
+    x, r = jittered_lattice_spheres(dims, np_, radius, rng)
     U = uniform_velocities(rng, len(r), vamp)
     return BoxSpec(dims=dims, tau=0.6, mapping=0, x=x, r=r, U=U, Om=np.zeros_like(U), u0=None)
 

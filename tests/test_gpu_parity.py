@@ -44,6 +44,8 @@ RAGGED = [
     ((70, 21, 18), (16, 16, 2), 3, True),
     ((33, 40, 27), (128, 2, 8), 6, True),
     ((24, 24, 24), (256, 1, 32), 2, False),
+    ((45, 38, 31), (64, 4, 8, 1), 5, False),
+    ((52, 33, 29), (32, 8, 2, 1), 4, True),
 ]
 
 
@@ -151,3 +153,39 @@ def test_tile_capacity_error_is_reported():
     assert e.value.code == psm.PSM_ECAPACITY
     eng.set_particles(0, x[:4], r[:4], np.zeros((4, 3)))
     eng.step(1)
+
+
+def test_velocity_only_update_keeps_lists_and_uses_new_velocities():
+    """Re-setting the spheres with the same positions and radii but new
+    velocities skips the re-binning; the next step must use the new U, Omega."""
+    spec = inputs.random_small((40, 32, 30), 5, (3.0, 4.5), seed=71, tau=0.66, omamp=0.002)
+    f0 = initial_f(spec)
+    eng = make_engine([spec])
+    eng.set_pdfs(0, f0)
+    eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+    eng.step(3)
+    f_mid = eng.get_pdfs(0).cpu().numpy()
+    rng = np.random.default_rng(3)
+    U2 = inputs.uniform_velocities(rng, len(spec.r), 0.02)
+    Om2 = inputs.uniform_velocities(rng, len(spec.r), 0.003)
+    eng.set_particles(0, spec.x, spec.r, U2, Om2)
+    eng.step(4)
+    f = eng.get_pdfs(0).cpu().numpy()
+    F, T = eng.get_forces(0)
+    spec2 = inputs.BoxSpec(dims=spec.dims, tau=spec.tau, fext=spec.fext, x=spec.x, r=spec.r, U=U2, Om=Om2)
+    ref = run_oracle(spec2, 4, f0=f_mid)
+    assert_pdfs_close(f, ref.f, 1e-12)
+    assert_forces_close(F, ref.F, ref.A)
+    assert_forces_close(T, ref.T, ref.A, lever=spec.r.max() + 1)
+
+
+def test_many_tiles_multi_chunk_scan():
+    """A box with more than ten thousand tiles (tile 16 x 16 x 1): the tile
+    scan runs over many chunks."""
+    spec = inputs.random_small((200, 160, 40), 12, (3.0, 6.0), seed=81, tau=0.75, fext=(0, 0, 2e-6))
+    steps = 3
+    ref = run_oracle(spec, steps)
+    f, F, T, B, pid, eng = run_engine(spec, steps, launch=(16, 16, 1, 0))
+    assert_pdfs_close(f, ref.f, 1e-12)
+    assert np.array_equal(pid, ref.pid)
+    assert_forces_close(F, ref.F, ref.A)

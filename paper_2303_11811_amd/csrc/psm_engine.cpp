@@ -75,7 +75,7 @@ struct Layout {
     size_t off_boxes, off_tbase, off_partbox, off_pt, off_acc, off_tcnt, off_toff, off_tpid, off_partial,
         off_misc, off_statpart, off_scan, total;
     std::vector<size_t> off_grid[2];
-    std::vector<long long> qstride;
+    std::vector<int> pblk;
     int T_max;
     long long cap_max;
     int P_total;
@@ -94,6 +94,9 @@ static int validate(const psm_box_desc* boxes, int nbox, int storage) {
         if (d.nx < 4 || d.ny < 4 || d.nz < 4) return fail(PSM_EINVAL, "box %d: every dimension must be >= 4", b);
         long long N = (long long)d.nx * d.ny * d.nz;
         if (N > 0x7fffffffLL) return fail(PSM_EINVAL, "box %d: more than 2^31-1 cells", b);
+        // byte offsets inside a z-plane are 32-bit
+        if ((long long)d.nx * d.ny * NQ * 8 + 64LL * NQ * 8 >= (1LL << 32))
+            return fail(PSM_EINVAL, "box %d: z-planes larger than 2^32 bytes", b);
         if (!(d.tau > 0.5) || !std::isfinite(d.tau)) return fail(PSM_EINVAL, "box %d: tau must be > 1/2", b);
         for (int a = 0; a < 3; ++a)
             if (!std::isfinite(d.fext[a])) return fail(PSM_EINVAL, "box %d: non-finite body force", b);
@@ -158,12 +161,12 @@ static Layout make_layout(const psm_box_desc* boxes, int nbox, int storage) {
     L.off_statpart = take(sizeof(double) * 4 * (size_t)stats_blocks() + 64);
     L.off_scan = take(sizeof(int) * 2 * (size_t)scan_chunks(Tmax) + 64);
     for (int p = 0; p < 2; ++p) L.off_grid[p].resize(nbox);
-    L.qstride.resize(nbox);
+    L.pblk.resize(nbox);
     for (int b = 0; b < nbox; ++b) {
-        long long N = (long long)boxes[b].nx * boxes[b].ny * boxes[b].nz;
-        long long qs = (N + 63) / 64 * 64;   // each q array starts 512-byte aligned (FP64)
-        L.qstride[b] = qs;
-        for (int p = 0; p < 2; ++p) L.off_grid[p][b] = take(s * NQ * (size_t)qs);
+        int pb = cdiv((long long)boxes[b].nx * boxes[b].ny, BLK);   // 64-cell blocks per z-plane
+        L.pblk[b] = pb;
+        size_t elems = (size_t)boxes[b].nz * pb * NQ * BLK;
+        for (int p = 0; p < 2; ++p) L.off_grid[p][b] = take(s * elems);
     }
     L.total = o;
     return L;
@@ -336,7 +339,8 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
         bx.np = 0;
         bx.mapping = d.mapping;
         bx.nsub = d.mapping == PSM_MAP_SUBSAMPLE ? d.subsample_n : 1;
-        bx.qstride = L.qstride[b];
+        bx.pblk = L.pblk[b];
+        bx.plane_elems = (long long)L.pblk[b] * NQ * BLK;
         bx.grid[0] = c->ws + L.off_grid[0][b];
         bx.grid[1] = c->ws + L.off_grid[1][b];
         bx.omega = 1.0 / d.tau;

@@ -12,6 +12,7 @@ constexpr int WG = 256;          // threads per workgroup of the step kernel
 constexpr int NWAVE = WG / 64;   // 64-wide wavefronts per workgroup
 constexpr int MAXC = 64;         // sphere candidates per tile staged in LDS
 constexpr int NXCD = 8;          // MI355X: 8 accelerator complex dies, 32 CUs each
+constexpr int BLK = 64;          // cells per PDF storage block (one wavefront)
 
 // D3Q19 velocity set in the canonical order of the ABI (psm.h). Directions
 // come in inverse pairs (2k-1, 2k) for k = 1..9.
@@ -26,8 +27,11 @@ struct BoxDev {
     int nx, ny, nz, N;
     int ntx, nty, ntz, tile_base;   // tiles per axis, first global tile
     int part_base, np, mapping, nsub;
-    long long qstride;              // elements between consecutive q arrays
-    void* grid[2];                  // ping-pong PDF grids [19][qstride]
+    // PDF storage: each z-plane holds pblk blocks of 64 cells (nx*ny rounded
+    // up); a block stores its 19 directions one after another, 64 values each.
+    int pblk;                       // blocks per z-plane
+    long long plane_elems;          // values per z-plane, pblk * 19 * 64
+    void* grid[2];                  // ping-pong PDF grids, nz * plane_elems values
     double omega, pref;             // 1/tau, 1 - 1/(2 tau)
     double g[3];                    // body-force density
     // Forcing constants of eq. (8) with the Guo prefactor, precomputed on the
@@ -90,6 +94,12 @@ __host__ __device__ inline AxisTiles axis_tiles(int lo, int hi, int L, int T, in
 __host__ __device__ inline void aabb_cells(double x, double r, int& lo, int& hi) {
     lo = (int)floor(x - (r + 1.0));
     hi = (int)floor(x + (r + 1.0));
+}
+
+// Element index of direction q of cell (x, y, z) in a box's PDF grid.
+__host__ __device__ inline long long pdf_index(const BoxDev& b, int q, int x, int y, int z) {
+    int s = x + b.nx * y;
+    return (long long)z * b.plane_elems + (long long)(s / BLK) * (NQ * BLK) + q * BLK + (s % BLK);
 }
 
 // ---------------------------------------------------------------------------

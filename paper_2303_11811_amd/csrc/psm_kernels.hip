@@ -161,8 +161,12 @@ __device__ __forceinline__ void particle_velocity(int c, double dx, double dy, d
     vz = uz[c] + (ox[c] * dy - oy[c] * dx);
 }
 
+#ifndef PSM_WAVES_PER_EU
+#define PSM_WAVES_PER_EU 3
+#endif
 template <class S, int MAP>
-__global__ __launch_bounds__(WG) void k_psm_step(StepParams kp) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PSM_WAVES_PER_EU, 8))) void k_psm_step(
+    StepParams kp) {
     using R = typename S::R;
     using T = typename S::T;
 
@@ -230,7 +234,17 @@ __global__ __launch_bounds__(WG) void k_psm_step(StepParams kp) {
         const int xs = lane_ok ? x : 0, ys = lane_ok ? y : 0;
         const int xm = xs == 0 ? nx - 1 : xs - 1, xp = xs == nx - 1 ? 0 : xs + 1;
         const int ym = ys == 0 ? ny - 1 : ys - 1, yp = ys == ny - 1 ? 0 : ys + 1;
-        const long long qs = bx.qstride;
+        // byte offsets inside a z-plane of the nine (x, y) source columns;
+        // they do not depend on z
+        const int nxl = nx;
+        auto inplane = [nxl](int xx, int yy) -> unsigned {
+            int c = xx + nxl * yy;
+            return (unsigned)(((c / BLK) * (NQ * BLK) + (c % BLK)) * (int)sizeof(T));
+        };
+        const unsigned o00 = inplane(xs, ys), om0 = inplane(xm, ys), op0 = inplane(xp, ys);
+        const unsigned o0m = inplane(xs, ym), o0p = inplane(xs, yp);
+        const unsigned omm = inplane(xm, ym), opp = inplane(xp, yp), omp = inplane(xm, yp), opm = inplane(xp, ym);
+        const long long pbytes = bx.plane_elems * (long long)sizeof(T);
         const T* __restrict__ src = (const T*)bx.grid[kp.parity];
         T* __restrict__ dst = (T*)bx.grid[kp.parity ^ 1];
         const R omega = (R)bx.omega;
@@ -243,13 +257,14 @@ __global__ __launch_bounds__(WG) void k_psm_step(StepParams kp) {
             const int z = tcz * TZ + k;
             if (z >= nz) break;
             const double czc = z + 0.5;
-            // Per-q grid bases stay scalar: laundering them through an empty asm
-            // keeps the compiler from hoisting 2 x 19 64-bit addresses out of
-            // the loop into vector registers. Offsets are 32-bit bytes.
-            long long qsb = qs * (long long)sizeof(T);
-            const GCHAR* sb = (const GCHAR*)src;
-            GLOBAL char* db = (GLOBAL char*)dst;
-            asm volatile("" : "+s"(qsb), "+s"(sb), "+s"(db));
+            const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+            // scalar plane bases of the source planes z-1, z, z+1 and the
+            // destination plane z; directions are 64 values apart in a block
+            const GCHAR* sbz = (const GCHAR*)src + z * pbytes;
+            const GCHAR* sbm = (const GCHAR*)src + zm * pbytes;
+            const GCHAR* sbp = (const GCHAR*)src + zp * pbytes;
+            GLOBAL char* dbz = (GLOBAL char*)dst + z * pbytes;
+            constexpr int QB = BLK * (int)sizeof(T);
 
             // 1. solid fractions of this cell from the staged candidates (Sec. 2.3.2)
             int c0 = -1, c1 = -1;
@@ -273,34 +288,28 @@ __global__ __launch_bounds__(WG) void k_psm_step(StepParams kp) {
             const bool psm_wave = __ballot(c0 >= 0) != 0ull;
 
             // 2. pull: f_q(x) = grid[q][x - c_q]
-            const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-            const int r00 = nx * (ys + ny * z);
-            const int rm0 = nx * (ym + ny * z), rp0 = nx * (yp + ny * z);
-            const int r0m = nx * (ys + ny * zm), r0p = nx * (ys + ny * zp);
-            const int rmm = nx * (ym + ny * zm), rpp = nx * (yp + ny * zp);
-            const int rmp = nx * (ym + ny * zp), rpm = nx * (yp + ny * zm);
             R hx = 0, hy = 0, hz = 0;   // 2 j - U, for the force of eq. (21)
             if (lane_ok) {
                 R f[NQ];
-                f[0] = S::loadb(sb + 0 * qsb, (unsigned)(xs + r00) * (unsigned)sizeof(T), kp.h_inv);
-                f[1] = S::loadb(sb + 1 * qsb, (unsigned)(xm + r00) * (unsigned)sizeof(T), kp.h_inv);
-                f[2] = S::loadb(sb + 2 * qsb, (unsigned)(xp + r00) * (unsigned)sizeof(T), kp.h_inv);
-                f[3] = S::loadb(sb + 3 * qsb, (unsigned)(xs + rm0) * (unsigned)sizeof(T), kp.h_inv);
-                f[4] = S::loadb(sb + 4 * qsb, (unsigned)(xs + rp0) * (unsigned)sizeof(T), kp.h_inv);
-                f[5] = S::loadb(sb + 5 * qsb, (unsigned)(xs + r0m) * (unsigned)sizeof(T), kp.h_inv);
-                f[6] = S::loadb(sb + 6 * qsb, (unsigned)(xs + r0p) * (unsigned)sizeof(T), kp.h_inv);
-                f[7] = S::loadb(sb + 7 * qsb, (unsigned)(xm + rm0) * (unsigned)sizeof(T), kp.h_inv);
-                f[8] = S::loadb(sb + 8 * qsb, (unsigned)(xp + rp0) * (unsigned)sizeof(T), kp.h_inv);
-                f[9] = S::loadb(sb + 9 * qsb, (unsigned)(xm + rp0) * (unsigned)sizeof(T), kp.h_inv);
-                f[10] = S::loadb(sb + 10 * qsb, (unsigned)(xp + rm0) * (unsigned)sizeof(T), kp.h_inv);
-                f[11] = S::loadb(sb + 11 * qsb, (unsigned)(xm + r0m) * (unsigned)sizeof(T), kp.h_inv);
-                f[12] = S::loadb(sb + 12 * qsb, (unsigned)(xp + r0p) * (unsigned)sizeof(T), kp.h_inv);
-                f[13] = S::loadb(sb + 13 * qsb, (unsigned)(xm + r0p) * (unsigned)sizeof(T), kp.h_inv);
-                f[14] = S::loadb(sb + 14 * qsb, (unsigned)(xp + r0m) * (unsigned)sizeof(T), kp.h_inv);
-                f[15] = S::loadb(sb + 15 * qsb, (unsigned)(xs + rmm) * (unsigned)sizeof(T), kp.h_inv);
-                f[16] = S::loadb(sb + 16 * qsb, (unsigned)(xs + rpp) * (unsigned)sizeof(T), kp.h_inv);
-                f[17] = S::loadb(sb + 17 * qsb, (unsigned)(xs + rmp) * (unsigned)sizeof(T), kp.h_inv);
-                f[18] = S::loadb(sb + 18 * qsb, (unsigned)(xs + rpm) * (unsigned)sizeof(T), kp.h_inv);
+                f[0] = S::loadb(sbz + 0 * QB, o00, kp.h_inv);
+                f[1] = S::loadb(sbz + 1 * QB, om0, kp.h_inv);
+                f[2] = S::loadb(sbz + 2 * QB, op0, kp.h_inv);
+                f[3] = S::loadb(sbz + 3 * QB, o0m, kp.h_inv);
+                f[4] = S::loadb(sbz + 4 * QB, o0p, kp.h_inv);
+                f[5] = S::loadb(sbm + 5 * QB, o00, kp.h_inv);
+                f[6] = S::loadb(sbp + 6 * QB, o00, kp.h_inv);
+                f[7] = S::loadb(sbz + 7 * QB, omm, kp.h_inv);
+                f[8] = S::loadb(sbz + 8 * QB, opp, kp.h_inv);
+                f[9] = S::loadb(sbz + 9 * QB, omp, kp.h_inv);
+                f[10] = S::loadb(sbz + 10 * QB, opm, kp.h_inv);
+                f[11] = S::loadb(sbm + 11 * QB, om0, kp.h_inv);
+                f[12] = S::loadb(sbp + 12 * QB, op0, kp.h_inv);
+                f[13] = S::loadb(sbp + 13 * QB, om0, kp.h_inv);
+                f[14] = S::loadb(sbm + 14 * QB, op0, kp.h_inv);
+                f[15] = S::loadb(sbm + 15 * QB, o0m, kp.h_inv);
+                f[16] = S::loadb(sbp + 16 * QB, o0p, kp.h_inv);
+                f[17] = S::loadb(sbp + 17 * QB, o0m, kp.h_inv);
+                f[18] = S::loadb(sbm + 18 * QB, o0p, kp.h_inv);
 
                 // 3. moments, eqs. (6)-(7); U carries the f/2 shift
                 R rho = ((((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) +
@@ -317,8 +326,7 @@ __global__ __launch_bounds__(WG) void k_psm_step(StepParams kp) {
                 const R pu0 = (R)bx.pw[0] * Ug3, pu1 = (R)bx.pw[1] * Ug3, pu2 = (R)bx.pw[2] * Ug3;
 
                 // 4. collision; each pair is stored as soon as it is final
-                const unsigned ob = (unsigned)(xs + r00) * (unsigned)sizeof(T);
-#define PSM_STORE(Q) S::storeb(db + (Q) * qsb, ob, f[Q], kp.h_scale)
+#define PSM_STORE(Q) S::storeb(dbz + (Q) * QB, o00, f[Q], kp.h_scale)
                 if (!psm_wave) {
                     f[0] = f[0] + (omega * ((R)W0 * base - f[0]) - pu0);
                     PSM_STORE(0);
@@ -618,7 +626,7 @@ __global__ void k_set_pdfs(BoxDev bx, int parity, const double* __restrict__ f, 
         zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
         double v = f[(long long)q * bx.N + xs + (long long)bx.nx * (ys + (long long)bx.ny * zs)];
         if (S::DEV) v -= wq(q);
-        g[q * bx.qstride + n] = S::from_f64(v, scale);
+        g[pdf_index(bx, q, x, y, z)] = S::from_f64(v, scale);
     }
 }
 
@@ -642,7 +650,7 @@ __global__ void k_set_equilibrium(BoxDev bx, int parity, const double* __restric
         double vv = vx * vx + vy * vy + vz * vz;
         double rr = S::DEV ? r - 1.0 : r;   // deviation form: E_q - w_q
         double e = wq(q) * (rr + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
-        g[q * bx.qstride + n] = S::from_f64(e, scale);
+        g[pdf_index(bx, q, x, y, z)] = S::from_f64(e, scale);
     }
 }
 
@@ -658,7 +666,7 @@ __global__ void k_get_pdfs(BoxDev bx, int parity, double* __restrict__ f, float 
         xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
         ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
         zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
-        double v = S::to_f64(g[q * bx.qstride + xs + (long long)bx.nx * (ys + (long long)bx.ny * zs)], inv);
+        double v = S::to_f64(g[pdf_index(bx, q, xs, ys, zs)], inv);
         if (S::DEV) v += wq(q);
         f[(long long)q * bx.N + n] = v;
     }
@@ -678,7 +686,7 @@ __global__ void k_get_pdfs_at(BoxDev bx, int parity, const int* __restrict__ cel
         xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
         ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
         zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
-        double v = S::to_f64(g[q * bx.qstride + xs + (long long)bx.nx * (ys + (long long)bx.ny * zs)], inv);
+        double v = S::to_f64(g[pdf_index(bx, q, xs, ys, zs)], inv);
         if (S::DEV) v += wq(q);
         out[(long long)q * ncells + i] = v;
     }
@@ -698,7 +706,7 @@ __global__ void k_macroscopic(BoxDev bx, int parity, double* __restrict__ rho, d
         xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
         ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
         zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
-        double v = S::to_f64(g[q * bx.qstride + xs + (long long)bx.nx * (ys + (long long)bx.ny * zs)], inv);
+        double v = S::to_f64(g[pdf_index(bx, q, xs, ys, zs)], inv);
         if (S::DEV) v += wq(q);
         r += v;
         j[0] += v * CX[q]; j[1] += v * CY[q]; j[2] += v * CZ[q];
@@ -751,9 +759,10 @@ __global__ __launch_bounds__(256) void k_stats_partial(BoxDev bx, int parity, fl
     double m = 0, px = 0, py = 0, pz = 0;
     for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < bx.N;
          n += (long long)gridDim.x * blockDim.x) {
+        int x = n % bx.nx, y = (n / bx.nx) % bx.ny, z = n / ((long long)bx.nx * bx.ny);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            double v = S::to_f64(g[q * bx.qstride + n], inv);
+            double v = S::to_f64(g[pdf_index(bx, q, x, y, z)], inv);
             if (S::DEV) v += wq(q);
             m += v;
             px += v * CX[q]; py += v * CY[q]; pz += v * CZ[q];

@@ -111,11 +111,14 @@ int psm_get_macroscopic(psm_ctx* ctx, int box, double* rho, double* u);
 
 /* Set the spheres of box `box` (Sec. 3.1.1: positions, radii, then linear and
  * angular velocities). Host arrays, row-major: x (n,3), r (n), U (n,3),
- * omega (n,3) (NULL omega = 0). Positions are wrapped into the box. Radii
- * must lie in [1, max_radius]. The library computes f(r) of eq. (26) in FP64,
- * uploads through pinned staging and rebuilds the per-tile candidate lists;
- * PSM_ECAPACITY if n > max_particles or a tile would list more candidates than
- * the kernel stages (synchronises). */
+ * omega (n,3) (NULL omega = 0); they are copied before the call returns.
+ * Positions are wrapped into the box. Radii must lie in [1, max_radius]. The
+ * library computes f(r) of eq. (26) in FP64 and uploads through pinned staging
+ * (asynchronous). When positions or radii differ from the previous call it
+ * rebuilds the per-tile candidate lists, which synchronises and returns
+ * PSM_ECAPACITY if a tile would list more candidates than the kernel stages
+ * (the context then refuses to step until a valid set is given).
+ * PSM_ECAPACITY also if n > max_particles. */
 int psm_set_particles(psm_ctx* ctx, int box, int n, const double* x, const double* r,
                       const double* U, const double* omega);
 

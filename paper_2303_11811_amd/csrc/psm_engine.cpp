@@ -203,9 +203,15 @@ struct psm_ctx {
     int* d_scan = nullptr;               // scan scratch (chunk sums and maxima)
     // last uploaded positions and radii per box: unchanged geometry keeps the lists
     std::vector<std::vector<double>> last_xr;
-    // pinned host staging
+    // pinned host staging: two upload halves (reused once their copy has
+    // completed, tracked by events) and a read-back area
     double* h_stage = nullptr;
     size_t h_stage_n = 0;
+    size_t h_half = 0;               // doubles per upload half
+    double* h_read = nullptr;        // read-back area (forces, stats)
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    int stage_next = 0;
+    std::vector<std::vector<double>> last_r, last_fr;   // f(r) cache per box
     // graphs of 10 steps, one per starting parity
     bool use_graph = false;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -386,9 +392,15 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
     auto hip_ok = [&](hipError_t e, const char* what) {
         if (e != hipSuccess && err == PSM_OK) err = fail(PSM_EHIP, "%s: %s", what, hipGetErrorString(e));
     };
-    c->h_stage_n = std::max<size_t>(11 * P1 + 64, 6 * P1 + 64);
+    c->h_half = 11 * P1 + 64;
+    c->h_stage_n = 2 * c->h_half + 6 * P1 + 64;
     hip_ok(hipHostMalloc((void**)&c->h_stage, sizeof(double) * c->h_stage_n, hipHostMallocDefault), "hipHostMalloc");
     if (err) { delete c; return err; }
+    c->h_read = c->h_stage + 2 * c->h_half;
+    for (int h = 0; h < 2; ++h) hip_ok(hipEventCreateWithFlags(&c->stage_ev[h], hipEventDisableTiming), "event");
+    if (err) { (void)hipHostFree(c->h_stage); delete c; return err; }
+    c->last_r.assign(nbox, std::vector<double>());
+    c->last_fr.assign(nbox, std::vector<double>());
 
     std::vector<int> partbox(P1, 0);
     for (int b = 0; b < nbox; ++b)
@@ -417,6 +429,8 @@ extern "C" int psm_destroy(psm_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    for (int h = 0; h < 2; ++h)
+        if (c->stage_ev[h]) (void)hipEventDestroy(c->stage_ev[h]);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     delete c;
     return PSM_OK;
@@ -504,39 +518,56 @@ extern "C" int psm_set_particles(psm_ctx* c, int box, int n, const double* x, co
                 return fail(PSM_EINVAL, "particle %d: non-finite input", p);
         }
     }
-    // staging: 11 SoA columns of length n, in the order of the device table
+    // staging: 11 SoA columns of length n (stride m), in the order of the
+    // device table, in the upload half whose previous copy has completed
     int m = d.max_particles;
-    double* st = c->h_stage;
+    int h = c->stage_next;
+    c->stage_next ^= 1;
+    HIP_TRY(hipEventSynchronize(c->stage_ev[h]));
+    double* st = c->h_stage + (size_t)h * c->h_half;
     double Lx = d.nx, Ly = d.ny, Lz = d.nz;
+    std::vector<double>& lr = c->last_r[box];
+    std::vector<double>& lf = c->last_fr[box];
+    lr.resize(n, -1.0);
+    lf.resize(n, 0.0);
     for (int p = 0; p < n; ++p) {
         st[0 * m + p] = wrap_coord(x[3 * p + 0], Lx);
         st[1 * m + p] = wrap_coord(x[3 * p + 1], Ly);
         st[2 * m + p] = wrap_coord(x[3 * p + 2], Lz);
         st[3 * m + p] = r[p];
-        st[4 * m + p] = solid_fraction_offset(r[p]);
+        if (lr[p] != r[p]) {   // f(r) only depends on r
+            lr[p] = r[p];
+            lf[p] = solid_fraction_offset(r[p]);
+        }
+        st[4 * m + p] = lf[p];
         for (int a = 0; a < 3; ++a) {
             st[(5 + a) * m + p] = U[3 * p + a];
             st[(8 + a) * m + p] = omega ? omega[3 * p + a] : 0.0;
         }
     }
-    double* cols[11] = {c->P.x, c->P.y, c->P.z, c->P.r, c->P.fr, c->P.ux, c->P.uy, c->P.uz, c->P.ox, c->P.oy, c->P.oz};
+    // the 11 device columns are P_total apart: one strided copy moves them all
     int pb = c->box[box].part_base;
+    size_t P1 = (size_t)std::max(c->P_total, 1);
     if (n > 0)
-        for (int k = 0; k < 11; ++k)
-            HIP_TRY(hipMemcpyAsync(cols[k] + pb, st + (size_t)k * m, sizeof(double) * n, hipMemcpyHostToDevice,
-                                   c->stream));
+        HIP_TRY(hipMemcpy2DAsync(c->P.x + pb, sizeof(double) * P1, st, sizeof(double) * m, sizeof(double) * n, 11,
+                                 hipMemcpyHostToDevice, c->stream));
+    bool np_changed = c->np[box] != n;
+    if (np_changed) {
+        int* npst = (int*)(st + 11 * (size_t)m);
+        *npst = n;
+        HIP_TRY(hipMemcpyAsync(&c->d_boxes[box].np, npst, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    }
+    HIP_TRY(hipEventRecord(c->stage_ev[h], c->stream));
     // positions (wrapped) and radii decide the tile lists; velocities do not
-    std::vector<double> xr((size_t)4 * n);
-    std::memcpy(xr.data(), st, sizeof(double) * n);
-    std::memcpy(xr.data() + n, st + m, sizeof(double) * n);
-    std::memcpy(xr.data() + 2 * n, st + 2 * m, sizeof(double) * n);
-    std::memcpy(xr.data() + 3 * n, st + 3 * m, sizeof(double) * n);
-    bool same_geometry = c->have_particles_lists && c->np[box] == n && xr == c->last_xr[box];
+    bool same_geometry = c->have_particles_lists && !np_changed && (size_t)4 * n == c->last_xr[box].size();
+    for (int k = 0; k < 4 && same_geometry; ++k)
+        same_geometry = std::memcmp(c->last_xr[box].data() + (size_t)k * n, st + (size_t)k * m,
+                                    sizeof(double) * n) == 0;
     c->box[box].np = n;
     c->np[box] = n;
-    HIP_TRY(hipMemcpyAsync(&c->d_boxes[box].np, &c->box[box].np, sizeof(int), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));   // staging is reused by the next call
     if (same_geometry) return PSM_OK;
+    std::vector<double> xr((size_t)4 * n);
+    for (int k = 0; k < 4; ++k) std::memcpy(xr.data() + (size_t)k * n, st + (size_t)k * m, sizeof(double) * n);
     c->last_xr[box].swap(xr);
     rc = rebuild_lists(c);
     if (rc != PSM_OK) c->last_xr[box].clear();
@@ -647,7 +678,7 @@ extern "C" int psm_get_forces(psm_ctx* c, int box, double* F, double* T) {
     int n = c->np[box];
     if (n == 0) return PSM_OK;
     if (!F || !T) return fail(PSM_EINVAL, "F/T is NULL");
-    double* st = c->h_stage;
+    double* st = c->h_read;
     HIP_TRY(hipMemcpyAsync(st, c->P.acc + 6LL * c->box[box].part_base, sizeof(double) * 6 * n,
                            hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -677,7 +708,7 @@ extern "C" int psm_get_stats(psm_ctx* c, int box, double* mass, double* momentum
     unsigned long long* dropped = (unsigned long long*)(c->d_misc + 8);
     HIP_TRY(hipMemsetAsync(dropped, 0, sizeof(unsigned long long), c->stream));
     HIP_TRY(launch_map_dense(c->box[box], c->P, c->d_toff, c->d_tpid, c->ts, nullptr, nullptr, dropped, c->stream));
-    double* st = c->h_stage;
+    double* st = c->h_read;
     HIP_TRY(hipMemcpyAsync(st, out, sizeof(double) * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(st + 4, dropped, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));

@@ -189,3 +189,28 @@ def test_many_tiles_multi_chunk_scan():
     assert_pdfs_close(f, ref.f, 1e-12)
     assert np.array_equal(pid, ref.pid)
     assert_forces_close(F, ref.F, ref.A)
+
+
+def test_checkpoint_resume_bitwise():
+    """State = canonical PDFs + spheres: step(2n) equals step(n) -> save ->
+    new context -> restore -> step(n), bit for bit (forces too: the force
+    reduction has a fixed order)."""
+    spec = inputs.random_small((44, 36, 30), 5, (3.0, 4.5), seed=91, tau=0.61, fext=(1e-5, 0, 0), omamp=0.002)
+    f_full, F_full, T_full, *_ = run_engine(spec, 16, launch=(64, 4, 2, 0))
+    f_half, *_ = run_engine(spec, 8, launch=(64, 4, 2, 0))
+    f_res, F_res, T_res, *_ = run_engine(spec, 8, launch=(64, 4, 2, 0), f0=f_half)
+    assert np.array_equal(f_full, f_res)
+    assert np.array_equal(F_full, F_res) and np.array_equal(T_full, T_res)
+
+
+def test_nonfinite_state_is_reported():
+    spec = inputs.random_small((24, 20, 16), 2, (2.5, 3.0), seed=5, tau=0.7)
+    f0 = initial_f(spec)
+    f0[3, 777] = np.nan
+    eng = make_engine([spec])
+    eng.set_pdfs(0, f0)
+    eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+    eng.step(2)
+    with pytest.raises(psm.PsmError) as e:
+        eng.get_stats(0)
+    assert e.value.code == psm.PSM_ENONFINITE

@@ -45,17 +45,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(launch):
-    """HBM bytes per launch from committed rocprofv3 counters, if they were
-    taken on the current kernel source and launch shape."""
+def measured_traffic():
+    """(HBM bytes per launch, launch shape of the counter run) from the
+    committed rocprofv3 counters, if they were taken on the current kernel
+    source; (None, None) otherwise."""
     try:
         with open(COUNTER_FILE) as fh:
             c = json.load(fh)
     except (OSError, ValueError):
-        return None
-    if c.get("kernel_src_sha") != kernel_source_hash() or list(c.get("launch", [])) != list(launch):
-        return None
-    return c.get("hbm_bytes_per_launch")
+        return None, None
+    if c.get("kernel_src_sha") != kernel_source_hash():
+        return None, None
+    return c.get("hbm_bytes_per_launch"), c.get("launch")
 
 
 def run_case(psm, torch, spec, storage, steps, warmup, autotune, launch=None, full_loop=True):
@@ -331,7 +332,7 @@ def main():
 
     algo_bytes = spec.N * BYTES_PER_CELL[0]
     achieved = algo_bytes / (main_res["kernel_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(main_res["launch"])
+    traffic, traffic_launch = measured_traffic()
     out = {
         "metric": METRIC,
         "value": round(main_res["mlups"], 1),
@@ -357,6 +358,7 @@ def main():
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
+            "traffic_launch": traffic_launch,
             "kernel": "k_psm_step<f64>", "kernel_ms": round(main_res["kernel_ms"], 4),
             "algorithmic_bytes_per_launch": algo_bytes,
             "frac_of_stream_copy": round(achieved / copy_gbps, 4),

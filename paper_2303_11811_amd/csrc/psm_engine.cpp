@@ -356,6 +356,7 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
             int q = 2 * k + 1;
             double cg = CX[q] * d.fext[0] + CY[q] * d.fext[1] + CZ[q] * d.fext[2];
             bx.fa[k] = 3.0 * bx.pref * wq(q) * cg;
+            bx.fa_scaled[k] = bx.fa[k] * (storage == PSM_FP16DEV ? fp16_scale : 1.0);
             bx.fs[k] = 9.0 * bx.pref * wq(q) * cg;
         }
         int dims[3] = {d.nx, d.ny, d.nz};

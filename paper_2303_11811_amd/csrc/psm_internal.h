@@ -39,6 +39,7 @@ struct BoxDev {
     //   F_q = fa[k] + fs[k] (c_q.U) - pw[class] 3 (U.g) for the pair k = (q, q+1),
     //   F_qbar = -fa[k] + fs[k] (c_q.U) - pw[class] 3 (U.g).
     double fa[9], fs[9];            // 3 pref w (c.g), 9 pref w (c.g)
+    double fa_scaled[9];            // fa times the FP16 storage scale
     double pw[3];                   // pref w for the rest, axis and diagonal weights
     // Geometry constants for the minimum image and the sub-sample test.
     double L[3], halfL[3];          // box lengths and their halves

@@ -51,6 +51,7 @@ struct St64 {
     using T = double;
     using R = double;
     static constexpr bool DEV = false;
+    static constexpr bool SCALED = false;
     __device__ static R loadb(const GCHAR* b, unsigned off, float) { return ld_pdf((const GLOBAL T*)(b + off)); }
     __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float) { st_pdf((GLOBAL T*)(b + off), v); }
     __device__ static double to_f64(T v, float) { return v; }
@@ -60,6 +61,7 @@ struct St32 {
     using T = float;
     using R = float;
     static constexpr bool DEV = true;
+    static constexpr bool SCALED = false;
     __device__ static R loadb(const GCHAR* b, unsigned off, float) { return ld_pdf((const GLOBAL T*)(b + off)); }
     __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float) { st_pdf((GLOBAL T*)(b + off), v); }
     __device__ static double to_f64(T v, float) { return (double)v; }
@@ -69,13 +71,13 @@ struct St16 {
     using T = _Float16;
     using R = float;
     static constexpr bool DEV = true;
+    // The step kernel works on the stored scaled deviations s d directly (the
+    // scale s is folded into the collision constants), so its loads and
+    // stores are bare conversions. State I/O converts with the scale.
+    static constexpr bool SCALED = true;
+    __device__ static R loadb(const GCHAR* b, unsigned off, float) { return (float)ld_pdf((const GLOBAL T*)(b + off)); }
+    __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float) { st_pdf((GLOBAL T*)(b + off), (_Float16)v); }
     // scale is a power of two: multiplication by it and by 1/scale is exact
-    __device__ static R loadb(const GCHAR* b, unsigned off, float inv) {
-        return (float)ld_pdf((const GLOBAL T*)(b + off)) * inv;
-    }
-    __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float scale) {
-        st_pdf((GLOBAL T*)(b + off), (_Float16)(v * scale));
-    }
     __device__ static double to_f64(T v, float inv) { return (double)((float)v * inv); }
     __device__ static T from_f64(double v, float scale) { return (_Float16)(float)(v * (double)scale); }
 };
@@ -109,11 +111,11 @@ template <class T> __device__ __forceinline__ const PSM_CONST T* cptr(const T* p
 // rho is the density deviation for the deviation storage forms.
 template <class R, int Q>
 __device__ __forceinline__ void pair_fluid(R& fq, R& fb, R base, R Ux, R Uy, R Uz, R fa, R fs, R pwUg3,
-                                           R omega) {
+                                           R omega, R k45) {
     constexpr R w = (R)wq(Q);
     constexpr R cx = (R)CX[Q], cy = (R)CY[Q], cz = (R)CZ[Q];
     R cu = cx * Ux + cy * Uy + cz * Uz;
-    R sU = w * base + ((R)4.5 * w) * (cu * cu);
+    R sU = w * base + (k45 * w) * (cu * cu);
     R aU = ((R)3.0 * w) * cu;
     R Fs = fs * cu - pwUg3;
     fq = fq + (omega * (sU + aU - fq) + (Fs + fa));
@@ -127,13 +129,13 @@ __device__ __forceinline__ void pair_fluid(R& fq, R& fb, R base, R Ux, R Uy, R U
 //   A0 = sum_s B_s (rho - 1.5 V_s.V_s), M = sum_s B_s V_s V_s^T, P = sum_s B_s V_s.
 template <class R, int Q>
 __device__ __forceinline__ void pair_psm(R& fq, R& fb, R base, R Ux, R Uy, R Uz, R fa, R fs, R pwUg3, R omega,
-                                         R Bt, R omB, R A0, R Mxx, R Myy, R Mzz, R Mxy, R Mxz, R Myz, R Px,
-                                         R Py, R Pz) {
+                                         R k45, R Bt, R omB, R A0, R Mxx, R Myy, R Mzz, R Mxy, R Mxz, R Myz,
+                                         R Px, R Py, R Pz) {
     constexpr R w = (R)wq(Q);
     constexpr int ix = CX[Q], iy = CY[Q], iz = CZ[Q];
     constexpr R cx = (R)ix, cy = (R)iy, cz = (R)iz;
     R cu = cx * Ux + cy * Uy + cz * Uz;
-    R sU = w * base + ((R)4.5 * w) * (cu * cu);
+    R sU = w * base + (k45 * w) * (cu * cu);
     R aU = ((R)3.0 * w) * cu;
     R Fs = fs * cu - pwUg3;
     R tq = omega * (sU + aU - fq) + (Fs + fa);
@@ -141,7 +143,7 @@ __device__ __forceinline__ void pair_psm(R& fq, R& fb, R base, R Ux, R Uy, R Uz,
     R cMc = (R)(ix * ix) * Mxx + (R)(iy * iy) * Myy + (R)(iz * iz) * Mzz +
             (R)(2 * ix * iy) * Mxy + (R)(2 * ix * iz) * Mxz + (R)(2 * iy * iz) * Myz;
     R cP = cx * Px + cy * Py + cz * Pz;
-    R sV = w * A0 + ((R)4.5 * w) * cMc;
+    R sV = w * A0 + (k45 * w) * cMc;
     R aV = ((R)3.0 * w) * cP;
     R Sq = Bt * (fb - (sU - aU) - fq) + (sV + aV);
     R Sb = Bt * (fq - (sU + aU) - fb) + (sV - aV);
@@ -249,6 +251,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PSM_WAVES_PE
         T* __restrict__ dst = (T*)bx.grid[kp.parity ^ 1];
         const R omega = (R)bx.omega;
         const R gx = (R)bx.g[0], gy = (R)bx.g[1], gz = (R)bx.g[2];
+        // scaled storage (FP16): the kernel works on s d; the quadratic terms
+        // carry 1/s and every particle velocity is multiplied by s
+        const R sc = S::SCALED ? (R)kp.h_scale : (R)1;
+        const R k15 = S::SCALED ? (R)1.5 * (R)kp.h_inv : (R)1.5;
+        const R k45 = S::SCALED ? (R)4.5 * (R)kp.h_inv : (R)4.5;
         const double Lx = bx.L[0], Ly = bx.L[1], Lz = bx.L[2];
         const double hLx = bx.halfL[0], hLy = bx.halfL[1], hLz = bx.halfL[2];
         const double cxc = xs + 0.5, cyc = ys + 0.5;
@@ -319,9 +326,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PSM_WAVES_PE
                 R jy = ((f[3] - f[4]) + (f[7] - f[8])) + ((f[10] - f[9]) + (f[15] - f[16])) + (f[17] - f[18]);
                 R jz = ((f[5] - f[6]) + (f[11] - f[12])) + ((f[14] - f[13]) + (f[15] - f[16])) + (f[18] - f[17]);
                 const R half = (R)0.5;
-                R Ux = jx + half * gx, Uy = jy + half * gy, Uz = jz + half * gz;
+                R Ux = jx + half * (sc * gx), Uy = jy + half * (sc * gy), Uz = jz + half * (sc * gz);
                 R uu = Ux * Ux + Uy * Uy + Uz * Uz;
-                R base = rho - (R)1.5 * uu;
+                R base = rho - k15 * uu;
                 R Ug3 = (R)3.0 * (Ux * gx + Uy * gy + Uz * gz);
                 const R pu0 = (R)bx.pw[0] * Ug3, pu1 = (R)bx.pw[1] * Ug3, pu2 = (R)bx.pw[2] * Ug3;
 
@@ -331,8 +338,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PSM_WAVES_PE
                     f[0] = f[0] + (omega * ((R)W0 * base - f[0]) - pu0);
                     PSM_STORE(0);
 #define PSM_PAIR(Q)                                                                                           \
-    pair_fluid<R, Q>(f[Q], f[Q + 1], base, Ux, Uy, Uz, (R)bx.fa[Q / 2], (R)bx.fs[Q / 2], Q < 7 ? pu1 : pu2, \
-                     omega);                                                                                  \
+    pair_fluid<R, Q>(f[Q], f[Q + 1], base, Ux, Uy, Uz, (R)(S::SCALED ? bx.fa_scaled[Q / 2] : bx.fa[Q / 2]),  \
+                     (R)bx.fs[Q / 2], Q < 7 ? pu1 : pu2, omega, k45);                                         \
     PSM_STORE(Q);                                                                                             \
     PSM_STORE(Q + 1)
                     PSM_PAIR(1); PSM_PAIR(3); PSM_PAIR(5); PSM_PAIR(7); PSM_PAIR(9);
@@ -346,9 +353,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PSM_WAVES_PE
                         double dx = min_image(cxc - s_px[c0], Lx, hLx), dy = min_image(cyc - s_py[c0], Ly, hLy),
                                dz = min_image(czc - s_pz[c0], Lz, hLz), vx, vy, vz;
                         particle_velocity(c0, dx, dy, dz, s_ux, s_uy, s_uz, s_ox, s_oy, s_oz, vx, vy, vz);
-                        R Vx = (R)vx, Vy = (R)vy, Vz = (R)vz, Bs = (R)B0;
+                        R Vx = sc * (R)vx, Vy = sc * (R)vy, Vz = sc * (R)vz, Bs = (R)B0;
                         Bt = Bs;
-                        A0 = Bs * (rho - (R)1.5 * (Vx * Vx + Vy * Vy + Vz * Vz));
+                        A0 = Bs * (rho - k15 * (Vx * Vx + Vy * Vy + Vz * Vz));
                         Px = Bs * Vx; Py = Bs * Vy; Pz = Bs * Vz;
                         Mxx = Px * Vx; Myy = Py * Vy; Mzz = Pz * Vz;
                         Mxy = Px * Vy; Mxz = Px * Vz; Myz = Py * Vz;
@@ -357,9 +364,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PSM_WAVES_PE
                         double dx = min_image(cxc - s_px[c1], Lx, hLx), dy = min_image(cyc - s_py[c1], Ly, hLy),
                                dz = min_image(czc - s_pz[c1], Lz, hLz), vx, vy, vz;
                         particle_velocity(c1, dx, dy, dz, s_ux, s_uy, s_uz, s_ox, s_oy, s_oz, vx, vy, vz);
-                        R Vx = (R)vx, Vy = (R)vy, Vz = (R)vz, Bs = (R)B1;
+                        R Vx = sc * (R)vx, Vy = sc * (R)vy, Vz = sc * (R)vz, Bs = (R)B1;
                         Bt = Bt + Bs;
-                        A0 = A0 + Bs * (rho - (R)1.5 * (Vx * Vx + Vy * Vy + Vz * Vz));
+                        A0 = A0 + Bs * (rho - k15 * (Vx * Vx + Vy * Vy + Vz * Vz));
                         R qx = Bs * Vx, qy = Bs * Vy, qz = Bs * Vz;
                         Px = Px + qx; Py = Py + qy; Pz = Pz + qz;
                         Mxx = Mxx + qx * Vx; Myy = Myy + qy * Vy; Mzz = Mzz + qz * Vz;
@@ -374,8 +381,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PSM_WAVES_PE
                         PSM_STORE(0);
                     }
 #define PSM_PAIR(Q)                                                                                       \
-    pair_psm<R, Q>(f[Q], f[Q + 1], base, Ux, Uy, Uz, (R)bx.fa[Q / 2], (R)bx.fs[Q / 2], Q < 7 ? pu1 : pu2, omega, \
-                   Bt, omB, A0, Mxx, Myy, Mzz, Mxy, Mxz, Myz, Px, Py, Pz);                                       \
+    pair_psm<R, Q>(f[Q], f[Q + 1], base, Ux, Uy, Uz, (R)(S::SCALED ? bx.fa_scaled[Q / 2] : bx.fa[Q / 2]),     \
+                   (R)bx.fs[Q / 2], Q < 7 ? pu1 : pu2, omega, k45, Bt, omB, A0, Mxx, Myy, Mzz, Mxy, Mxz, Myz, Px, \
+                   Py, Pz);                                                                                      \
     PSM_STORE(Q);                                                                                                \
     PSM_STORE(Q + 1)
                     PSM_PAIR(1); PSM_PAIR(3); PSM_PAIR(5); PSM_PAIR(7); PSM_PAIR(9);
@@ -404,7 +412,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PSM_WAVES_PE
                         double dx = min_image(cxc - s_px[c], Lx, hLx), dy = min_image(cyc - s_py[c], Ly, hLy),
                                dz = min_image(czc - s_pz[c], Lz, hLz), vx, vy, vz;
                         particle_velocity(c, dx, dy, dz, s_ux, s_uy, s_uz, s_ox, s_oy, s_oz, vx, vy, vz);
-                        R Vx = (R)vx, Vy = (R)vy, Vz = (R)vz;
+                        R Vx = sc * (R)vx, Vy = sc * (R)vy, Vz = sc * (R)vz;
+                        if (S::SCALED) Bs *= (double)kp.h_inv;
                         v[0] = Bs * (double)(hx - Vx);
                         v[1] = Bs * (double)(hy - Vy);
                         v[2] = Bs * (double)(hz - Vz);

@@ -255,7 +255,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--launch", type=str, default=None, help="tx,ty,tz,persistent (skips the autotuner)")
+    ap.add_argument("--launch", type=str, default=None, help="tx,ty,tz,flags (skips the autotuner)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--kernel-only", action="store_true", help="time psm_step alone (no upload/readback)")
     ap.add_argument("--precision-steps", type=int, default=200)

@@ -145,22 +145,29 @@ int psm_get_solid_fraction(psm_ctx* ctx, int box, double* B, int* pid);
  * Synchronises. PSM_ENONFINITE if mass or momentum is not finite. */
 int psm_get_stats(psm_ctx* ctx, int box, double* mass, double* momentum, long long* slot_overflows);
 
+/* Launch options of the step kernel (bit flags). */
+enum psm_launch_flags {
+    PSM_LAUNCH_PERSISTENT = 1,  /* grid sized to the workgroups that fit on the chip at once, each
+                                   walking a contiguous share of the tiles (else one workgroup per tile) */
+    PSM_LAUNCH_FILTER = 2       /* per wave and z, test each staged sphere against the rectangle of
+                                   the wave's cells first; the per-cell mapping of Sec. 2.3.2 then
+                                   visits only spheres that can reach them (same results) */
+};
+
 /* Launch shape of the step kernel: a tile of tx*ty threads (tx*ty == 256,
  * tx in {16,32,64,128,256}) handling tz cells each along z (tz in
- * {1,2,4,8,16,32}); persistent = 1 sizes the grid to the workgroups that fit
- * on the chip at once, each walking a contiguous share of the tiles, 0
- * launches one workgroup per tile. Rebuilds the tile lists (synchronises);
- * invalidates captured graphs. On failure the previous shape is restored.
- * psm_get_launch: host outputs (persistent may be NULL). */
-int psm_set_launch(psm_ctx* ctx, int tx, int ty, int tz, int persistent);
-int psm_get_launch(psm_ctx* ctx, int* tx, int* ty, int* tz, int* persistent);
+ * {1,2,4,8,16,32}), and psm_launch_flags. Rebuilds the tile lists
+ * (synchronises); invalidates captured graphs. On failure the previous
+ * launch is restored. psm_get_launch: host outputs (flags may be NULL). */
+int psm_set_launch(psm_ctx* ctx, int tx, int ty, int tz, int flags);
+int psm_get_launch(psm_ctx* ctx, int* tx, int* ty, int* tz, int* flags);
 
-/* Time every allowed launch shape and grid mode on this context with HIP
- * events (warmup + trial_steps steps each), keep the fastest and report it
- * (host outputs, each may be NULL). The trial steps advance and overwrite
+/* Time every allowed launch shape and flag combination on this context with
+ * HIP events (warmup + trial_steps steps each), keep the fastest and report
+ * it (host outputs, each may be NULL). The trial steps advance and overwrite
  * the PDF state: set the state after tuning. Synchronises. best_ms: ms per
  * step of the chosen launch. */
-int psm_autotune(psm_ctx* ctx, int trial_steps, int* tx, int* ty, int* tz, int* persistent, double* best_ms);
+int psm_autotune(psm_ctx* ctx, int trial_steps, int* tx, int* ty, int* tz, int* flags, double* best_ms);
 
 /* Enable (1) / disable (0) HIP-graph replay of 10-step sequences in psm_step. */
 int psm_set_graph(psm_ctx* ctx, int enable);

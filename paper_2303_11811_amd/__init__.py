@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libpsm.so")
 PSM_OK, PSM_EINVAL, PSM_EHIP, PSM_ECAPACITY, PSM_ENONFINITE, PSM_ESTATE = 0, -1, -2, -3, -4, -6
 PSM_FP64, PSM_FP32DEV, PSM_FP16DEV = 0, 1, 2
 PSM_MAP_LINEAR, PSM_MAP_SUBSAMPLE = 0, 1
+PSM_LAUNCH_PERSISTENT, PSM_LAUNCH_FILTER = 1, 2
 STORAGE = {"f64": PSM_FP64, "f32dev": PSM_FP32DEV, "f16dev": PSM_FP16DEV}
 
 
@@ -193,8 +194,8 @@ def psm_get_stats(ctx, box):
     return mass.value, mom, int(ov.value)
 
 
-def psm_set_launch(ctx, tx, ty, tz, persistent=0):
-    return _check(lib().psm_set_launch(ctx, int(tx), int(ty), int(tz), int(persistent)))
+def psm_set_launch(ctx, tx, ty, tz, flags=0):
+    return _check(lib().psm_set_launch(ctx, int(tx), int(ty), int(tz), int(flags)))
 
 
 def psm_get_launch(ctx):
@@ -348,8 +349,8 @@ class Engine:
     def get_stats(self, box=0):
         return psm_get_stats(self.ctx, box)
 
-    def set_launch(self, tx, ty, tz, persistent=0):
-        psm_set_launch(self.ctx, tx, ty, tz, persistent)
+    def set_launch(self, tx, ty, tz, flags=0):
+        psm_set_launch(self.ctx, tx, ty, tz, flags)
 
     def get_launch(self):
         return psm_get_launch(self.ctx)

@@ -49,7 +49,7 @@ extern "C" const char* psm_last_error(void) { return g_err.c_str(); }
 // Launch shapes
 
 static const int kTX[] = {16, 32, 64, 128, 256};
-static const int kTZ[] = {1, 2, 4, 8, 16, 32};
+static const int kTZ[] = {1, 2, 4, 8, 16, TZ_MAX};
 
 static bool shape_allowed(int tx, int ty, int tz) {
     bool okx = false, okz = false;
@@ -186,7 +186,7 @@ struct psm_ctx {
     std::vector<BoxDev> box;     // host copy of the device box table
     std::vector<int> np;         // particles set per box
     int P_total = 0;
-    TileShape ts{64, 4, 16, 0};
+    TileShape ts{64, 4, 16, 0, 0};
     int T_total = 0;
     int grid = 0;
     int parity = 0;
@@ -260,7 +260,7 @@ static void assign_tiles(psm_ctx* c) {
     // one-shot: a workgroup per tile (rounded up to whole XCD rounds);
     // persistent: as many workgroups as fit at once, each walking its tiles
     int full = ((c->T_total + NXCD - 1) / NXCD) * NXCD;
-    int g = c->ts.persistent ? std::min(step_blocks_per_cu(c->storage, c->map_mode) * ncu, full) : full;
+    int g = c->ts.persistent ? std::min(step_blocks_per_cu(c->storage, c->map_mode, c->ts.filter != 0) * ncu, full) : full;
     c->grid = std::max(NXCD, g / NXCD * NXCD);
 }
 
@@ -623,7 +623,7 @@ static int enqueue_step(psm_ctx* c, bool timed) {
         e1 = next_event(c);
         if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
     }
-    HIP_TRY(launch_step(c->storage, c->map_mode, kp, c->grid, c->stream));
+    HIP_TRY(launch_step(c->storage, c->map_mode, c->ts.filter != 0, kp, c->grid, c->stream));
     if (timed && e1) HIP_TRY(hipEventRecord(e1, c->stream));
     HIP_TRY(launch_reduce(reduce_params(c), c->stream));
     c->parity ^= 1;
@@ -724,13 +724,13 @@ extern "C" int psm_get_stats(psm_ctx* c, int box, double* mass, double* momentum
     return PSM_OK;
 }
 
-extern "C" int psm_set_launch(psm_ctx* c, int tx, int ty, int tz, int persistent) {
+extern "C" int psm_set_launch(psm_ctx* c, int tx, int ty, int tz, int flags) {
     if (!c) return fail(PSM_EINVAL, "ctx is NULL");
     if (!shape_allowed(tx, ty, tz)) return fail(PSM_EINVAL, "launch shape %dx%dx%d not allowed", tx, ty, tz);
-    if (persistent != 0 && persistent != 1) return fail(PSM_EINVAL, "persistent must be 0 or 1");
+    if (flags & ~(PSM_LAUNCH_PERSISTENT | PSM_LAUNCH_FILTER)) return fail(PSM_EINVAL, "unknown launch flags %d", flags);
     HIP_TRY(hipStreamSynchronize(c->stream));
     TileShape old = c->ts;
-    c->ts = TileShape{tx, ty, tz, persistent};
+    c->ts = TileShape{tx, ty, tz, (flags & PSM_LAUNCH_PERSISTENT) ? 1 : 0, (flags & PSM_LAUNCH_FILTER) ? 1 : 0};
     assign_tiles(c);
     int rc = upload_box_table(c);
     if (rc == PSM_OK) rc = rebuild_lists(c);
@@ -746,10 +746,14 @@ extern "C" int psm_set_launch(psm_ctx* c, int tx, int ty, int tz, int persistent
     return PSM_OK;
 }
 
-extern "C" int psm_get_launch(psm_ctx* c, int* tx, int* ty, int* tz, int* persistent) {
+static int launch_flags(const TileShape& t) {
+    return (t.persistent ? PSM_LAUNCH_PERSISTENT : 0) | (t.filter ? PSM_LAUNCH_FILTER : 0);
+}
+
+extern "C" int psm_get_launch(psm_ctx* c, int* tx, int* ty, int* tz, int* flags) {
     if (!c || !tx || !ty || !tz) return fail(PSM_EINVAL, "NULL argument");
     *tx = c->ts.tx; *ty = c->ts.ty; *tz = c->ts.tz;
-    if (persistent) *persistent = c->ts.persistent;
+    if (flags) *flags = launch_flags(c->ts);
     return PSM_OK;
 }
 
@@ -790,7 +794,7 @@ extern "C" int psm_reset_timing(psm_ctx* c) {
     return PSM_OK;
 }
 
-extern "C" int psm_autotune(psm_ctx* c, int trial_steps, int* tx, int* ty, int* tz, int* persistent,
+extern "C" int psm_autotune(psm_ctx* c, int trial_steps, int* tx, int* ty, int* tz, int* flags,
                             double* best_ms) {
     if (!c) return fail(PSM_EINVAL, "ctx is NULL");
     if (trial_steps < 1) return fail(PSM_EINVAL, "trial_steps must be >= 1");
@@ -804,13 +808,13 @@ extern "C" int psm_autotune(psm_ctx* c, int trial_steps, int* tx, int* ty, int* 
     HIP_TRY(hipEventCreate(&e1));
     int maxdim = 0;
     for (auto& d : c->desc) maxdim = std::max(maxdim, d.nx);
-    for (int pers = 0; pers < 2; ++pers)
+    for (int fl = 0; fl < 4; ++fl)
     for (int txv : kTX) {
         // tiles much wider than the widest box only idle lanes
         if (txv > 2 * std::max(maxdim, 16)) continue;
         for (int tzv : kTZ) {
             int tyv = WG / txv;
-            if (psm_set_launch(c, txv, tyv, tzv, pers) != PSM_OK) continue;
+            if (psm_set_launch(c, txv, tyv, tzv, fl) != PSM_OK) continue;
             int rc = psm_step(c, 2);
             if (rc) break;
             (void)hipEventRecord(e0, c->stream);
@@ -831,12 +835,12 @@ extern "C" int psm_autotune(psm_ctx* c, int trial_steps, int* tx, int* ty, int* 
     (void)hipEventDestroy(e1);
     c->timing = was_timing;
     c->use_graph = was_graph;
-    int rc = psm_set_launch(c, best.tx, best.ty, best.tz, best.persistent);
+    int rc = psm_set_launch(c, best.tx, best.ty, best.tz, launch_flags(best));
     if (rc) return rc;
     if (tx) *tx = best.tx;
     if (ty) *ty = best.ty;
     if (tz) *tz = best.tz;
-    if (persistent) *persistent = best.persistent;
+    if (flags) *flags = launch_flags(best);
     if (best_ms) *best_ms = best_t;
     return PSM_OK;
 }

@@ -11,6 +11,7 @@ constexpr int NQ = 19;
 constexpr int WG = 256;          // threads per workgroup of the step kernel
 constexpr int NWAVE = WG / 64;   // 64-wide wavefronts per workgroup
 constexpr int MAXC = 64;         // sphere candidates per tile staged in LDS
+constexpr int TZ_MAX = 32;   // largest cells per thread along z of a tile
 constexpr int NXCD = 8;          // MI355X: 8 accelerator complex dies, 32 CUs each
 constexpr int BLK = 64;          // cells per PDF storage block (one wavefront)
 
@@ -56,6 +57,7 @@ struct Particles {
 struct TileShape {
     int tx, ty, tz;
     int persistent;   // 1: occupancy-sized grid walking the tiles; 0: one workgroup per tile
+    int filter;       // 1: per-wave candidate filter before the per-cell mapping
 };
 
 // ---------------------------------------------------------------------------
@@ -242,8 +244,8 @@ struct BinParams {
     TileShape ts;
 };
 
-hipError_t launch_step(int storage, int map, const StepParams& kp, int grid, hipStream_t st);
-int step_blocks_per_cu(int storage, int map);
+hipError_t launch_step(int storage, int map, bool filt, const StepParams& kp, int grid, hipStream_t st);
+int step_blocks_per_cu(int storage, int map, bool filt);
 hipError_t launch_reduce(const ReduceParams& rp, hipStream_t st);
 int scan_chunks(int n);
 hipError_t launch_bin(const BinParams& bp, int* stats, int* scratch, hipStream_t st);

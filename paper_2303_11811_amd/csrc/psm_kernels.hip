@@ -163,11 +163,46 @@ __device__ __forceinline__ void particle_velocity(int c, double dx, double dy, d
     vz = uz[c] + (ox[c] * dy - oy[c] * dx);
 }
 
+// Waves per SIMD the register budget of the step kernel is cut for: 3 for
+// FP64 and FP16 storage (168 VGPRs), 4 for FP32 storage (128 VGPRs). Under
+// the 128-register cap the FP16 form serialises its 19 loads.
 #ifndef PSM_WAVES_PER_EU
 #define PSM_WAVES_PER_EU 3
 #endif
-template <class S, int MAP>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PSM_WAVES_PER_EU, 8))) void k_psm_step(
+#ifndef PSM_WAVES_PER_EU_F32
+#define PSM_WAVES_PER_EU_F32 4
+#endif
+// 1: the values of the next z cell are loaded before the current cell is
+// collided, so a wave keeps 19 loads in flight during its arithmetic.
+#ifndef PSM_PREFETCH
+#define PSM_PREFETCH 0
+#endif
+
+// pull of the 19 values of one cell: planes z (bz), z-1 (bm), z+1 (bp)
+#define PSM_LOAD19(F, bz, bm, bp)                      \
+    do {                                               \
+        F[0] = S::loadb(bz + 0 * QB, o00, kp.h_inv);   \
+        F[1] = S::loadb(bz + 1 * QB, om0, kp.h_inv);   \
+        F[2] = S::loadb(bz + 2 * QB, op0, kp.h_inv);   \
+        F[3] = S::loadb(bz + 3 * QB, o0m, kp.h_inv);   \
+        F[4] = S::loadb(bz + 4 * QB, o0p, kp.h_inv);   \
+        F[5] = S::loadb(bm + 5 * QB, o00, kp.h_inv);   \
+        F[6] = S::loadb(bp + 6 * QB, o00, kp.h_inv);   \
+        F[7] = S::loadb(bz + 7 * QB, omm, kp.h_inv);   \
+        F[8] = S::loadb(bz + 8 * QB, opp, kp.h_inv);   \
+        F[9] = S::loadb(bz + 9 * QB, omp, kp.h_inv);   \
+        F[10] = S::loadb(bz + 10 * QB, opm, kp.h_inv); \
+        F[11] = S::loadb(bm + 11 * QB, om0, kp.h_inv); \
+        F[12] = S::loadb(bp + 12 * QB, op0, kp.h_inv); \
+        F[13] = S::loadb(bp + 13 * QB, om0, kp.h_inv); \
+        F[14] = S::loadb(bm + 14 * QB, op0, kp.h_inv); \
+        F[15] = S::loadb(bm + 15 * QB, o0m, kp.h_inv); \
+        F[16] = S::loadb(bp + 16 * QB, o0p, kp.h_inv); \
+        F[17] = S::loadb(bp + 17 * QB, o0m, kp.h_inv); \
+        F[18] = S::loadb(bm + 18 * QB, o0p, kp.h_inv); \
+    } while (0)
+template <class S, int MAP, bool FILT>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typename S::T) == 4 ? PSM_WAVES_PER_EU_F32 : PSM_WAVES_PER_EU, 8))) void k_psm_step(
     StepParams kp) {
     using R = typename S::R;
     using T = typename S::T;
@@ -176,6 +211,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PSM_WAVES_PE
     __shared__ double s_ux[MAXC], s_uy[MAXC], s_uz[MAXC], s_ox[MAXC], s_oy[MAXC], s_oz[MAXC];
     __shared__ int s_pid[MAXC];
     __shared__ double s_acc[NWAVE][6][MAXC];
+    __shared__ unsigned long long s_cmask[NWAVE][TZ_MAX];
 
     const int tid = threadIdx.x;
     const int TX = kp.tx, TY = kp.ty, TZ = kp.tz;
@@ -259,6 +295,45 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PSM_WAVES_PE
         const double Lx = bx.L[0], Ly = bx.L[1], Lz = bx.L[2];
         const double hLx = bx.halfL[0], hLy = bx.halfL[1], hLz = bx.halfL[2];
         const double cxc = xs + 0.5, cyc = ys + 0.5;
+        // Candidate filter: bit c of s_cmask[wave][k] is set if candidate c
+        // can reach a cell of this wave at the tile's k-th z: the distance from
+        // the sphere centre to the rectangle of the wave's cell centres (lanes
+        // past the box edge only enlarge it) is below r + f(r), or r + the
+        // sampling reach, plus a margin that covers the FP32 rounding of the
+        // test. Other candidates give zero fraction to all of those cells.
+        if (FILT && nc > 0) {
+            float xy2 = 0.0f, pz = 0.0f, lim2 = -1.0f;
+            if (lane < nc) {
+                const int wwx = TX < 64 ? TX : 64, wwy = TX < 64 ? 64 / TX : 1;
+                const int wx0 = tcx * TX + (64 * wave) % TX, wy0 = tcy * TY + (64 * wave) / TX;
+                double ex = fabs(min_image(wx0 + 0.5 * wwx - s_px[lane], bx.L[0], bx.halfL[0])) - 0.5 * (wwx - 1);
+                double ey = fabs(min_image(wy0 + 0.5 * wwy - s_py[lane], bx.L[1], bx.halfL[1])) - 0.5 * (wwy - 1);
+                ex = ex > 0.0 ? ex : 0.0;
+                ey = ey > 0.0 ? ey : 0.0;
+                xy2 = (float)(ex * ex + ey * ey);
+                pz = (float)s_pz[lane];
+                const double lim = s_pr[lane] + (MAP == 0 ? s_pfr[lane] : bx.reach) + 0.05;
+                lim2 = (float)(lim * lim);
+            }
+            const float fnz = (float)nz;
+            for (int k = 0; k < TZ; ++k) {
+                float ez = (float)(tcz * TZ + k) + 0.5f - pz;
+                ez = ez >= 0.5f * fnz ? ez - fnz : (ez < -0.5f * fnz ? ez + fnz : ez);
+                const unsigned long long m = __ballot(xy2 + ez * ez < lim2);
+                if (lane == 0) s_cmask[wave][k] = m;
+            }
+        }
+
+        constexpr int QB = BLK * (int)sizeof(T);
+        const GCHAR* const src_c = (const GCHAR*)src;
+        auto plane = [&](int zz) -> const GCHAR* {
+            return src_c + (zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz)) * pbytes;
+        };
+        R fnext[NQ];
+        if (PSM_PREFETCH) {
+            const int z0 = tcz * TZ;
+            if (lane_ok && z0 < nz) PSM_LOAD19(fnext, plane(z0), plane(z0 - 1), plane(z0 + 1));
+        }
 
         for (int k = 0; k < TZ; ++k) {
             const int z = tcz * TZ + k;
@@ -271,52 +346,58 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(PSM_WAVES_PE
             const GCHAR* sbm = (const GCHAR*)src + zm * pbytes;
             const GCHAR* sbp = (const GCHAR*)src + zp * pbytes;
             GLOBAL char* dbz = (GLOBAL char*)dst + z * pbytes;
-            constexpr int QB = BLK * (int)sizeof(T);
 
-            // 1. solid fractions of this cell from the staged candidates (Sec. 2.3.2)
+            // 1. solid fractions of this cell from the staged candidates (Sec. 2.3.2);
+            // with the filter, only the candidates that can reach this wave at this z
             int c0 = -1, c1 = -1;
             double B0 = 0.0, B1 = 0.0;
-            if (nc > 0) {
+#define PSM_MAP_ONE(c)                                                                                       \
+    do {                                                                                                    \
+        double dx = min_image(cxc - s_px[c], Lx, hLx);                                                      \
+        double dy = min_image(cyc - s_py[c], Ly, hLy);                                                      \
+        double dz = min_image(czc - s_pz[c], Lz, hLz);                                                      \
+        double B = MAP == 0 ? overlap_linear(dx, dy, dz, s_pr[c], s_pfr[c])                                 \
+                            : overlap_subsample(dx, dy, dz, s_pr[c], bx.nsub, bx.sub_off, bx.reach);         \
+        if (B > 0.0) slots_insert(sl, c, s_pid[c], B);                                                      \
+    } while (0)
+            if constexpr (FILT) {
+                unsigned long long cm = nc > 0 ? s_cmask[wave][k] : 0ull;
+                if (cm != 0ull) {
+                    Slots sl;
+                    slots_init(sl);
+                    if (lane_ok) {
+                        while (cm != 0ull) {
+                            const int c = __ffsll((long long)cm) - 1;
+                            cm &= cm - 1ull;
+                            PSM_MAP_ONE(c);
+                        }
+                        slots_finish(sl);
+                    }
+                    c0 = sl.c0; c1 = sl.c1; B0 = sl.B0; B1 = sl.B1;
+                }
+            } else if (nc > 0) {
                 Slots sl;
                 slots_init(sl);
                 if (lane_ok) {
-                    for (int c = 0; c < nc; ++c) {
-                        double dx = min_image(cxc - s_px[c], Lx, hLx);
-                        double dy = min_image(cyc - s_py[c], Ly, hLy);
-                        double dz = min_image(czc - s_pz[c], Lz, hLz);
-                        double B = MAP == 0 ? overlap_linear(dx, dy, dz, s_pr[c], s_pfr[c])
-                                            : overlap_subsample(dx, dy, dz, s_pr[c], bx.nsub, bx.sub_off, bx.reach);
-                        if (B > 0.0) slots_insert(sl, c, s_pid[c], B);
-                    }
+                    for (int c = 0; c < nc; ++c) PSM_MAP_ONE(c);
                     slots_finish(sl);
                 }
                 c0 = sl.c0; c1 = sl.c1; B0 = sl.B0; B1 = sl.B1;
             }
+#undef PSM_MAP_ONE
             const bool psm_wave = __ballot(c0 >= 0) != 0ull;
 
             // 2. pull: f_q(x) = grid[q][x - c_q]
             R hx = 0, hy = 0, hz = 0;   // 2 j - U, for the force of eq. (21)
             if (lane_ok) {
                 R f[NQ];
-                f[0] = S::loadb(sbz + 0 * QB, o00, kp.h_inv);
-                f[1] = S::loadb(sbz + 1 * QB, om0, kp.h_inv);
-                f[2] = S::loadb(sbz + 2 * QB, op0, kp.h_inv);
-                f[3] = S::loadb(sbz + 3 * QB, o0m, kp.h_inv);
-                f[4] = S::loadb(sbz + 4 * QB, o0p, kp.h_inv);
-                f[5] = S::loadb(sbm + 5 * QB, o00, kp.h_inv);
-                f[6] = S::loadb(sbp + 6 * QB, o00, kp.h_inv);
-                f[7] = S::loadb(sbz + 7 * QB, omm, kp.h_inv);
-                f[8] = S::loadb(sbz + 8 * QB, opp, kp.h_inv);
-                f[9] = S::loadb(sbz + 9 * QB, omp, kp.h_inv);
-                f[10] = S::loadb(sbz + 10 * QB, opm, kp.h_inv);
-                f[11] = S::loadb(sbm + 11 * QB, om0, kp.h_inv);
-                f[12] = S::loadb(sbp + 12 * QB, op0, kp.h_inv);
-                f[13] = S::loadb(sbp + 13 * QB, om0, kp.h_inv);
-                f[14] = S::loadb(sbm + 14 * QB, op0, kp.h_inv);
-                f[15] = S::loadb(sbm + 15 * QB, o0m, kp.h_inv);
-                f[16] = S::loadb(sbp + 16 * QB, o0p, kp.h_inv);
-                f[17] = S::loadb(sbp + 17 * QB, o0m, kp.h_inv);
-                f[18] = S::loadb(sbm + 18 * QB, o0p, kp.h_inv);
+                if (PSM_PREFETCH) {
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) f[q] = fnext[q];
+                    if (k + 1 < TZ && z + 1 < nz) PSM_LOAD19(fnext, sbp, sbz, plane(z + 2));
+                } else {
+                    PSM_LOAD19(f, sbz, sbm, sbp);
+                }
 
                 // 3. moments, eqs. (6)-(7); U carries the f/2 shift
                 R rho = ((((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) +
@@ -813,34 +894,32 @@ __global__ __launch_bounds__(256) void k_stream_copy(const double2* __restrict__
 
 static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-template <int MAP>
-static hipError_t launch_step_map(int storage, const StepParams& kp, int grid, hipStream_t st) {
+// The step kernel instance for (storage, map, filt): storage psm_storage;
+// map 0 when every box uses the linear approximation, 1 if any box samples;
+// filt the per-wave candidate filter.
+template <int MAP, bool FILT>
+static const void* step_kernel_of(int storage) {
     switch (storage) {
-        case 0: hipLaunchKernelGGL((k_psm_step<St64, MAP>), dim3(grid), dim3(WG), 0, st, kp); break;
-        case 1: hipLaunchKernelGGL((k_psm_step<St32, MAP>), dim3(grid), dim3(WG), 0, st, kp); break;
-        default: hipLaunchKernelGGL((k_psm_step<St16, MAP>), dim3(grid), dim3(WG), 0, st, kp); break;
+        case 0: return (const void*)k_psm_step<St64, MAP, FILT>;
+        case 1: return (const void*)k_psm_step<St32, MAP, FILT>;
+        default: return (const void*)k_psm_step<St16, MAP, FILT>;
     }
-    return hipGetLastError();
 }
 
-// map: 0 when every box uses the linear approximation, 1 if any box samples.
-hipError_t launch_step(int storage, int map, const StepParams& kp, int grid, hipStream_t st) {
-    return map ? launch_step_map<1>(storage, kp, grid, st) : launch_step_map<0>(storage, kp, grid, st);
+static const void* step_kernel(int storage, int map, bool filt) {
+    if (map) return filt ? step_kernel_of<1, true>(storage) : step_kernel_of<1, false>(storage);
+    return filt ? step_kernel_of<0, true>(storage) : step_kernel_of<0, false>(storage);
 }
 
-template <int MAP>
-static int blocks_per_cu_map(int storage) {
+hipError_t launch_step(int storage, int map, bool filt, const StepParams& kp, int grid, hipStream_t st) {
+    void* args[] = {(void*)&kp};
+    return hipLaunchKernel(step_kernel(storage, map, filt), dim3(grid), dim3(WG), args, 0, st);
+}
+
+int step_blocks_per_cu(int storage, int map, bool filt) {
     int nb = 0;
-    switch (storage) {
-        case 0: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_psm_step<St64, MAP>, WG, 0); break;
-        case 1: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_psm_step<St32, MAP>, WG, 0); break;
-        default: (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_psm_step<St16, MAP>, WG, 0); break;
-    }
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel(storage, map, filt), WG, 0);
     return nb > 0 ? nb : 1;
-}
-
-int step_blocks_per_cu(int storage, int map) {
-    return map ? blocks_per_cu_map<1>(storage) : blocks_per_cu_map<0>(storage);
 }
 
 hipError_t launch_reduce(const ReduceParams& rp, hipStream_t st) {

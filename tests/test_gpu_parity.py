@@ -20,12 +20,13 @@ def _print_case(name, **kw):
     print(f"[case] {name} {kw}", flush=True)
 
 
-def test_parity_32_subsample_100_steps():
+@pytest.mark.parametrize("launch", [None, (32, 8, 4, psm.PSM_LAUNCH_FILTER)])
+def test_parity_32_subsample_100_steps(launch):
     """32^3, tau 0.6, Taylor-Green start, 8 spheres r=4 with 4^3 sampling."""
     spec = inputs.parity_32(seed=0)
-    _print_case("parity_32", steps=100)
+    _print_case("parity_32", steps=100, launch=launch)
     ref = run_oracle(spec, 100)
-    f, F, T, B, pid, eng = run_engine(spec, 100)
+    f, F, T, B, pid, eng = run_engine(spec, 100, launch=launch)
     assert_pdfs_close(f, ref.f, 1e-12)
     assert np.array_equal(pid, ref.pid)
     assert np.array_equal(B, ref.B)
@@ -46,6 +47,11 @@ RAGGED = [
     ((24, 24, 24), (256, 1, 32), 2, False),
     ((45, 38, 31), (64, 4, 8, 1), 5, False),
     ((52, 33, 29), (32, 8, 2, 1), 4, True),
+    # with the per-wave candidate filter (flag 2), also combined with the persistent grid
+    ((40, 36, 20), (64, 4, 4, 2), 4, False),
+    ((70, 21, 18), (16, 16, 2, 2), 3, True),
+    ((33, 40, 27), (128, 2, 8, 3), 6, True),
+    ((24, 24, 24), (256, 1, 32, 2), 2, False),
 ]
 
 
@@ -214,3 +220,22 @@ def test_nonfinite_state_is_reported():
     with pytest.raises(psm.PsmError) as e:
         eng.get_stats(0)
     assert e.value.code == psm.PSM_ENONFINITE
+
+
+@pytest.mark.parametrize("storage", [psm.PSM_FP64, psm.PSM_FP32DEV, psm.PSM_FP16DEV])
+def test_candidate_filter_is_exact(storage):
+    """The per-wave candidate filter only skips spheres that give zero
+    fraction, so every storage form produces bitwise the same PDFs, forces and
+    slots with and without it, here on a dense packing (many candidates per
+    tile, overlapping spheres, ragged tiles, both mappings)."""
+    for mapping, dims in ((psm.PSM_MAP_LINEAR, (72, 50, 36)), (psm.PSM_MAP_SUBSAMPLE, (40, 34, 30))):
+        spec = inputs.random_small(dims, 40, (2.0, 5.0), seed=11, tau=0.7, fext=(1e-5, 0, -2e-6),
+                                   vamp=0.01, omamp=0.003, overlap=True, mapping=mapping)
+        _print_case("filter", storage=storage, mapping=mapping, dims=dims, n=len(spec.r))
+        out = []
+        for launch in ((32, 8, 4, 0), (32, 8, 4, psm.PSM_LAUNCH_FILTER)):
+            f, F, T, B, pid, eng = run_engine(spec, 6, storage=storage, launch=launch)
+            eng.close()
+            out.append((f, F, T, B, pid))
+        for a, b in zip(*out):
+            assert np.array_equal(a, b)

@@ -9,7 +9,9 @@ wrapper, written from arXiv 2303.11811:
 * Sec. 2.3, eqs. (17)-(22): partially saturated cells collision, particle
   velocity at the cell centre, hydrodynamic force and torque;
 * Sec. 2.3.2, eqs. (25)-(27): linear-approximation solid fraction (and the
-  sub-division sampling it is compared with).
+  sub-division sampling it is compared with);
+* Sec. 2.2.2, eqs. (15)-(16): velocity-Verlet update of the spheres (and the
+  explicit Euler update of the moving-particle workload).
 
 The C header comment of ``psm_oracle.c`` lists every reading taken where the
 paper is silent. Everything here is FP64.
@@ -76,6 +78,8 @@ def _load():
         lib.psmo_run.argtypes = [bp, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D, _D, _D,
                                  _D, _D, _D, _D, _I]
         lib.psmo_run.restype = ctypes.c_longlong
+        lib.psmo_integrate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D, _D,
+                                       _D, _D, _D, _D, _D, _D, _D, _D, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -231,3 +235,36 @@ def run(box: Box, f0, nsteps, x=None, r=None, U=None, Om=None, frv=None) -> Resu
                                         _dp(res.T), _dp(res.A), _dp(res.B), _ip(res.pid)))
     res.f = f
     return res
+
+
+EULER = 0
+VERLET = 1
+
+
+class Dynamics:
+    """Particle state of the integrator: positions x, velocities U, angular
+    velocities Om (n,3) and, for velocity Verlet, the previous total force
+    and torque."""
+
+    def __init__(self, x, r, U, Om):
+        self.x = _f64(x, (-1, 3)).copy()
+        self.r = _f64(r, (-1,)).copy()
+        self.U = _f64(U, (-1, 3)).copy()
+        self.Om = _f64(Om, (-1, 3)).copy()
+        self.Fprev = np.zeros_like(self.x)
+        self.Tprev = np.zeros_like(self.x)
+        self.have_prev = False
+
+
+def integrate(box: Box, dyn: Dynamics, F, T, dt=1.0, scheme=VERLET, rho_p=1.0, accel=(0.0, 0.0, 0.0)):
+    """One particle update of dyn in place from the hydrodynamic force and
+    torque F, T (n,3) of the fluid step just done (psmo_integrate)."""
+    F = _f64(F, (-1, 3))
+    T = _f64(T, (-1, 3))
+    L = np.array([box.nx, box.ny, box.nz], dtype=np.float64)
+    a = _f64(accel, (3,))
+    _load().psmo_integrate(len(dyn.r), int(scheme), float(dt), float(rho_p), _dp(a), _dp(L), _dp(dyn.r),
+                           _dp(dyn.x), _dp(dyn.U), _dp(dyn.Om), _dp(F), _dp(T), _dp(dyn.Fprev),
+                           _dp(dyn.Tprev), int(dyn.have_prev))
+    if scheme == VERLET:
+        dyn.have_prev = True

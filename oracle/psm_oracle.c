@@ -12,6 +12,8 @@
  *   Sec. 2.1   lattice Boltzmann method, eqs. (1)-(8)
  *   Sec. 2.3   partially saturated cells method, eqs. (17)-(22)
  *   Sec. 2.3.2 particle mapping (linear approximation), eqs. (25)-(27)
+ *   Sec. 2.2.2 particle integration, eqs. (15)-(16) (velocity Verlet), and
+ *              the explicit Euler update of the moving-particle workload
  *
  * Scheme: push form exactly as eqs. (1)-(2) are written. The state f(x,t) is
  * the pre-collision PDF field. One step = map particles -> collide every cell
@@ -489,4 +491,61 @@ long long psmo_run(const psmo_box *b, int nsteps, int np, const double *x, const
     free(fnew);
     free(slots);
     return overflow;
+}
+
+/* ------------------------------------------------------------------ */
+/* Particle integration (Sec. 2.2.2) for spheres without collisions.    */
+/*
+ * Mass and moment of inertia of a homogeneous sphere of radius r and density
+ * ratio rho_p (fluid density 1): m = rho_p (4/3) pi r^3, I = (2/5) m r^2.
+ * The total force is the hydrodynamic force plus m * accel (an external
+ * acceleration such as gravity minus buoyancy); the torque is hydrodynamic.
+ *
+ * scheme 0, explicit Euler:   x += dt U;  U += dt F/m;  Om += dt T/I.
+ * scheme 1, velocity Verlet of eqs. (15)-(16), called once after each fluid
+ * step with that step's force F (taken at the positions x it used):
+ *   if have_prev:  U  += dt/(2m) (F_prev + F),  Om += dt/(2I) (T_prev + T)
+ *   then           x  += dt U + dt^2/(2m) F,    F_prev = F, T_prev = T.
+ * Positions are wrapped into [0, L) afterwards. Arrays (n,3) row-major,
+ * updated in place. */
+static double wrap_coord(double v, double L)
+{
+    double w = fmod(v, L);
+    if (w < 0.0) w += L;
+    if (w >= L) w -= L;
+    return w;
+}
+
+void psmo_integrate(int n, int scheme, double dt, double rho_p, const double *accel, const double *Lbox,
+                    const double *r, double *x, double *U, double *Om, const double *F, const double *T,
+                    double *Fprev, double *Tprev, int have_prev)
+{
+    const double pi = 3.14159265358979323846;
+    for (int p = 0; p < n; ++p) {
+        double m = rho_p * (4.0 / 3.0) * pi * r[p] * r[p] * r[p];
+        double I = 0.4 * m * r[p] * r[p];
+        double Ft[3], Tt[3];
+        for (int a = 0; a < 3; ++a) {
+            Ft[a] = F[3 * p + a] + m * accel[a];
+            Tt[a] = T[3 * p + a];
+        }
+        if (scheme == 0) {
+            for (int a = 0; a < 3; ++a) {
+                x[3 * p + a] += dt * U[3 * p + a];
+                U[3 * p + a] += dt * Ft[a] / m;
+                Om[3 * p + a] += dt * Tt[a] / I;
+            }
+        } else {
+            for (int a = 0; a < 3; ++a) {
+                if (have_prev) {
+                    U[3 * p + a] += dt / (2.0 * m) * (Fprev[3 * p + a] + Ft[a]);
+                    Om[3 * p + a] += dt / (2.0 * I) * (Tprev[3 * p + a] + Tt[a]);
+                }
+                x[3 * p + a] += dt * U[3 * p + a] + dt * dt / (2.0 * m) * Ft[a];
+                Fprev[3 * p + a] = Ft[a];
+                Tprev[3 * p + a] = Tt[a];
+            }
+        }
+        for (int a = 0; a < 3; ++a) x[3 * p + a] = wrap_coord(x[3 * p + a], Lbox[a]);
+    }
 }

@@ -118,7 +118,8 @@ int psm_get_macroscopic(psm_ctx* ctx, int box, double* rho, double* u);
  * rebuilds the per-tile candidate lists, which synchronises and returns
  * PSM_ECAPACITY if a tile would list more candidates than the kernel stages
  * (the context then refuses to step until a valid set is given).
- * PSM_ECAPACITY also if n > max_particles. */
+ * PSM_ECAPACITY also if n > max_particles. psm_get_forces and psm_get_stats
+ * also report a device-side list overflow after psm_integrate. */
 int psm_set_particles(psm_ctx* ctx, int box, int n, const double* x, const double* r,
                       const double* U, const double* omega);
 
@@ -144,6 +145,36 @@ int psm_get_solid_fraction(psm_ctx* ctx, int box, double* B, int* pid);
  * dropped third-or-later overlaps of the current mapping (may be NULL).
  * Synchronises. PSM_ENONFINITE if mass or momentum is not finite. */
 int psm_get_stats(psm_ctx* ctx, int box, double* mass, double* momentum, long long* slot_overflows);
+
+/* Sphere dynamics (Sec. 2.2.2) on the device, for collision-free spheres.
+ * m = rho_p (4/3) pi r^3 and I = (2/5) m r^2 (fluid density 1); the total force
+ * is the hydrodynamic force of the last executed step plus m * accel, the
+ * torque is the hydrodynamic torque. */
+enum psm_scheme {
+    PSM_EULER = 0,   /* x += dt U; U += dt F/m; Omega += dt T/I */
+    PSM_VERLET = 1   /* velocity Verlet, eqs. (15)-(16): U completed with the previous and the
+                        new force (once a previous force exists), then x += dt U + dt^2 F/(2m) */
+};
+
+/* Density ratio rho_p > 0 and external acceleration accel (host double[3],
+ * NULL = 0) of the spheres of box `box`. Defaults: 1 and 0. Synchronises. */
+int psm_set_dynamics(psm_ctx* ctx, int box, double density_ratio, const double* accel);
+
+/* Advance every sphere of every box by one update of `scheme` (psm_scheme)
+ * with time step dt > 0, using the force and torque of the last executed
+ * step; positions are wrapped into the box. Then rebuild the per-tile
+ * candidate lists on the device. Asynchronous: nothing is read back. If the
+ * moved spheres put more than 64 candidates into a tile, the lists are cut
+ * there (the step stays in bounds but its results are not valid) and the next
+ * psm_get_forces / psm_get_stats / psm_get_particles returns PSM_ECAPACITY;
+ * the context then refuses to step until psm_set_particles. psm_set_particles
+ * restarts velocity Verlet (its first update has no previous force). */
+int psm_integrate(psm_ctx* ctx, double dt, int scheme);
+
+/* Current positions x, velocities U and angular velocities omega of the
+ * spheres of box `box` (host (n,3) each, any may be NULL). Synchronises;
+ * reports a device-side list overflow as psm_integrate describes. */
+int psm_get_particles(psm_ctx* ctx, int box, double* x, double* U, double* omega);
 
 /* Launch options of the step kernel (bit flags). */
 enum psm_launch_flags {

@@ -22,6 +22,7 @@ PSM_OK, PSM_EINVAL, PSM_EHIP, PSM_ECAPACITY, PSM_ENONFINITE, PSM_ESTATE = 0, -1,
 PSM_FP64, PSM_FP32DEV, PSM_FP16DEV = 0, 1, 2
 PSM_MAP_LINEAR, PSM_MAP_SUBSAMPLE = 0, 1
 PSM_LAUNCH_PERSISTENT, PSM_LAUNCH_FILTER = 1, 2
+PSM_EULER, PSM_VERLET = 0, 1
 STORAGE = {"f64": PSM_FP64, "f32dev": PSM_FP32DEV, "f16dev": PSM_FP16DEV}
 
 
@@ -66,6 +67,9 @@ _SIGS = {
     "psm_set_timing": ([_P, ctypes.c_int], ctypes.c_int),
     "psm_get_timing": ([_P, ctypes.POINTER(ctypes.c_longlong), _D], ctypes.c_int),
     "psm_reset_timing": ([_P], ctypes.c_int),
+    "psm_set_dynamics": ([_P, ctypes.c_int, ctypes.c_double, _D], ctypes.c_int),
+    "psm_integrate": ([_P, ctypes.c_double, ctypes.c_int], ctypes.c_int),
+    "psm_get_particles": ([_P, ctypes.c_int, _D, _D, _D], ctypes.c_int),
     "psm_stream_copy": ([_P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "psm_last_error": ([], ctypes.c_char_p),
 }
@@ -180,6 +184,21 @@ def psm_get_forces(ctx, box, n):
     T = np.zeros((n, 3))
     _check(lib().psm_get_forces(ctx, box, _dptr(F), _dptr(T)))
     return F, T
+
+
+def psm_set_dynamics(ctx, box, density_ratio, accel=None):
+    a = None if accel is None else np.ascontiguousarray(accel, dtype=np.float64).reshape(3)
+    return _check(lib().psm_set_dynamics(ctx, box, float(density_ratio), _dptr(a)))
+
+
+def psm_integrate(ctx, dt, scheme):
+    return _check(lib().psm_integrate(ctx, float(dt), int(scheme)))
+
+
+def psm_get_particles(ctx, box, n):
+    x, U, Om = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 3))
+    _check(lib().psm_get_particles(ctx, box, _dptr(x), _dptr(U), _dptr(Om)))
+    return x, U, Om
 
 
 def psm_get_solid_fraction(ctx, box, B_ptr, pid_ptr):
@@ -338,6 +357,15 @@ class Engine:
 
     def get_forces(self, box=0):
         return psm_get_forces(self.ctx, box, self.np[box])
+
+    def set_dynamics(self, box, density_ratio, accel=None):
+        psm_set_dynamics(self.ctx, box, density_ratio, accel)
+
+    def integrate(self, dt=1.0, scheme=PSM_VERLET):
+        psm_integrate(self.ctx, dt, scheme)
+
+    def get_particles(self, box=0):
+        return psm_get_particles(self.ctx, box, self.np[box])
 
     def get_solid_fraction(self, box=0):
         with self._enter():

@@ -72,8 +72,8 @@ static int max_tiles_axis(double rmax, int T, int L) {
 // Workspace layout
 
 struct Layout {
-    size_t off_boxes, off_tbase, off_partbox, off_pt, off_acc, off_tcnt, off_toff, off_tpid, off_partial,
-        off_misc, off_statpart, off_scan, total;
+    size_t off_boxes, off_tbase, off_partbox, off_pt, off_acc, off_fprev, off_prevok, off_tcnt, off_toff, off_tpid,
+        off_partial, off_misc, off_statpart, off_scan, total;
     std::vector<size_t> off_grid[2];
     std::vector<int> pblk;
     int T_max;
@@ -153,6 +153,8 @@ static Layout make_layout(const psm_box_desc* boxes, int nbox, int storage) {
     L.off_partbox = take(sizeof(int) * std::max(P, 1));
     L.off_pt = take(sizeof(double) * 11 * std::max(P, 1));
     L.off_acc = take(sizeof(double) * 6 * std::max(P, 1));
+    L.off_fprev = take(sizeof(double) * 6 * std::max(P, 1));
+    L.off_prevok = take(sizeof(int) * std::max(P, 1));
     L.off_tcnt = take(sizeof(int) * (size_t)Tmax);
     L.off_toff = take(sizeof(int) * ((size_t)Tmax + 1));
     L.off_tpid = take(sizeof(int) * (size_t)L.cap_max);
@@ -191,6 +193,7 @@ struct psm_ctx {
     int grid = 0;
     int parity = 0;
     bool have_particles_lists = false;
+    bool lists_unchecked = false;   // rebuilt on the device after an integration
     // device pointers into the workspace
     BoxDev* d_boxes = nullptr;
     int* d_tbase = nullptr;
@@ -198,7 +201,7 @@ struct psm_ctx {
     Particles P{};
     int *d_tcnt = nullptr, *d_toff = nullptr, *d_tpid = nullptr;
     double* d_partial = nullptr;
-    int* d_misc = nullptr;               // [0..1] bin stats, [8..9] dropped (u64)
+    int* d_misc = nullptr;               // [0..1] bin stats, [8..9] dropped (u64), [16] device errors
     double* d_statpart = nullptr;
     int* d_scan = nullptr;               // scan scratch (chunk sums and maxima)
     // last uploaded positions and radii per box: unchanged geometry keeps the lists
@@ -278,9 +281,11 @@ static int rebuild_lists(psm_ctx* c) {
     bp.P_total = c->P_total;
     bp.T_total = c->T_total;
     bp.ts = c->ts;
+    bp.cap = c->L.cap_max;
     HIP_TRY(launch_bin(bp, c->d_misc, c->d_scan, c->stream));
     int stats[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(stats, c->d_misc, sizeof stats, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(launch_fill_int(c->d_misc + 16, 1, 0, c->stream));   // earlier device-side flags are void
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (stats[1] > c->L.cap_max)
         return fail(PSM_ECAPACITY, "tile lists need %d entries, capacity %lld", stats[1], c->L.cap_max);
@@ -289,7 +294,49 @@ static int rebuild_lists(psm_ctx* c) {
                     stats[0], MAXC);
     HIP_TRY(launch_bin_fill(bp, c->stream));
     c->have_particles_lists = true;
+    c->lists_unchecked = false;
     return PSM_OK;
+}
+
+// Rebuild the lists without waiting for the device: the counts are checked on
+// the device, which flags an overflow in d_misc[16] (the fill and the step
+// kernel stay in bounds); synchronising calls report it.
+static int rebuild_lists_async(psm_ctx* c) {
+    BinParams bp;
+    bp.boxes = c->d_boxes;
+    bp.part_box = c->d_partbox;
+    bp.P = c->P;
+    bp.tile_cnt = c->d_tcnt;
+    bp.tile_off = c->d_toff;
+    bp.tile_pid = c->d_tpid;
+    bp.P_total = c->P_total;
+    bp.T_total = c->T_total;
+    bp.ts = c->ts;
+    bp.cap = c->L.cap_max;
+    HIP_TRY(launch_bin(bp, c->d_misc, c->d_scan, c->stream));
+    HIP_TRY(launch_check_lists(c->d_misc, c->L.cap_max, c->d_misc + 16, c->stream));
+    HIP_TRY(launch_bin_fill(bp, c->stream));
+    c->lists_unchecked = true;
+    return PSM_OK;
+}
+
+// After a synchronisation: report (and clear) an overflow flagged by the
+// device since lists were last rebuilt there. The context then refuses to
+// step until psm_set_particles gives a valid set.
+static int device_errors(psm_ctx* c) {
+    if (!c->lists_unchecked) return PSM_OK;
+    int* e = (int*)(c->h_read + 9 * (size_t)std::max(c->P_total, 1));
+    HIP_TRY(hipMemcpyAsync(e, c->d_misc + 16, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (*e == 0) return PSM_OK;
+    int flags = *e;
+    *e = 0;
+    HIP_TRY(hipMemcpyAsync(c->d_misc + 16, e, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->have_particles_lists = false;
+    c->lists_unchecked = false;
+    if (flags & 1) return fail(PSM_ECAPACITY, "moved spheres need more tile-list entries than the context holds");
+    return fail(PSM_ECAPACITY, "moved spheres put more than %d candidates into a tile: use a smaller tile shape", MAXC);
 }
 
 extern "C" int psm_workspace_size(const psm_box_desc* boxes, int nbox, int storage, size_t* bytes) {
@@ -366,6 +413,7 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
         }
         for (int k = 0; k < 16; ++k) bx.sub_off[k] = k < bx.nsub ? (k + 0.5) / bx.nsub - 0.5 : 0.0;
         bx.reach = 0.8660254037844386 * (1.0 - 1.0 / bx.nsub) + 1e-9;
+        bx.rho_p = 1.0;
         bx.pw[0] = bx.pref * W0;
         bx.pw[1] = bx.pref * W1;
         bx.pw[2] = bx.pref * W2;
@@ -380,6 +428,8 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
                            &c->P.uy, &c->P.uz, &c->P.ox, &c->P.oy, &c->P.oz};
     for (int k = 0; k < 11; ++k) *fields[k] = pt + k * P1;
     c->P.acc = (double*)(c->ws + L.off_acc);
+    c->P.fprev = (double*)(c->ws + L.off_fprev);
+    c->P.prev_ok = (int*)(c->ws + L.off_prevok);
     c->d_tcnt = (int*)(c->ws + L.off_tcnt);
     c->d_toff = (int*)(c->ws + L.off_toff);
     c->d_tpid = (int*)(c->ws + L.off_tpid);
@@ -394,7 +444,7 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
         if (e != hipSuccess && err == PSM_OK) err = fail(PSM_EHIP, "%s: %s", what, hipGetErrorString(e));
     };
     c->h_half = 11 * P1 + 64;
-    c->h_stage_n = 2 * c->h_half + 6 * P1 + 64;
+    c->h_stage_n = 2 * c->h_half + 9 * P1 + 64;
     hip_ok(hipHostMalloc((void**)&c->h_stage, sizeof(double) * c->h_stage_n, hipHostMallocDefault), "hipHostMalloc");
     if (err) { delete c; return err; }
     c->h_read = c->h_stage + 2 * c->h_half;
@@ -410,6 +460,9 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
            "upload part_box");
     hip_ok(hipMemsetAsync(c->P.acc, 0, sizeof(double) * 6 * P1, c->stream), "clear forces");
     hip_ok(hipMemsetAsync(pt, 0, sizeof(double) * 11 * P1, c->stream), "clear particles");
+    hip_ok(hipMemsetAsync(c->P.fprev, 0, sizeof(double) * 6 * P1, c->stream), "clear previous forces");
+    hip_ok(hipMemsetAsync(c->P.prev_ok, 0, sizeof(int) * P1, c->stream), "clear previous-force flags");
+    hip_ok(hipMemsetAsync(c->d_misc, 0, 256, c->stream), "clear counters");
     hip_ok(hipStreamSynchronize(c->stream), "sync");
     if (err) { (void)hipHostFree(c->h_stage); delete c; return err; }
 
@@ -552,6 +605,8 @@ extern "C" int psm_set_particles(psm_ctx* c, int box, int n, const double* x, co
     if (n > 0)
         HIP_TRY(hipMemcpy2DAsync(c->P.x + pb, sizeof(double) * P1, st, sizeof(double) * m, sizeof(double) * n, 11,
                                  hipMemcpyHostToDevice, c->stream));
+    // new velocities: velocity Verlet starts again from this state
+    HIP_TRY(launch_fill_int(c->P.prev_ok + pb, m, 0, c->stream));
     bool np_changed = c->np[box] != n;
     if (np_changed) {
         int* npst = (int*)(st + 11 * (size_t)m);
@@ -683,6 +738,8 @@ extern "C" int psm_get_forces(psm_ctx* c, int box, double* F, double* T) {
     HIP_TRY(hipMemcpyAsync(st, c->P.acc + 6LL * c->box[box].part_base, sizeof(double) * 6 * n,
                            hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    rc = device_errors(c);
+    if (rc) return rc;
     for (int p = 0; p < n; ++p)
         for (int a = 0; a < 3; ++a) {
             F[3 * p + a] = st[6 * p + a];
@@ -713,6 +770,8 @@ extern "C" int psm_get_stats(psm_ctx* c, int box, double* mass, double* momentum
     HIP_TRY(hipMemcpyAsync(st, out, sizeof(double) * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(st + 4, dropped, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    rc = device_errors(c);
+    if (rc) return rc;
     if (mass) *mass = st[0];
     if (momentum)
         for (int a = 0; a < 3; ++a) momentum[a] = st[1 + a];
@@ -721,6 +780,66 @@ extern "C" int psm_get_stats(psm_ctx* c, int box, double* mass, double* momentum
     if (slot_overflows) *slot_overflows = (long long)dr;
     for (int k = 0; k < 4; ++k)
         if (!std::isfinite(st[k])) return fail(PSM_ENONFINITE, "box %d: non-finite mass or momentum", box);
+    return PSM_OK;
+}
+
+extern "C" int psm_set_dynamics(psm_ctx* c, int box, double density_ratio, const double* accel) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    if (!(density_ratio > 0.0) || !std::isfinite(density_ratio))
+        return fail(PSM_EINVAL, "density ratio must be positive and finite");
+    double a[3] = {0.0, 0.0, 0.0};
+    if (accel)
+        for (int k = 0; k < 3; ++k) {
+            if (!std::isfinite(accel[k])) return fail(PSM_EINVAL, "non-finite acceleration");
+            a[k] = accel[k];
+        }
+    BoxDev& bx = c->box[box];
+    bx.rho_p = density_ratio;
+    for (int k = 0; k < 3; ++k) bx.accel[k] = a[k];
+    return upload_box_table(c);
+}
+
+extern "C" int psm_integrate(psm_ctx* c, double dt, int scheme) {
+    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PSM_EINVAL, "dt must be positive and finite");
+    if (scheme != PSM_EULER && scheme != PSM_VERLET) return fail(PSM_EINVAL, "unknown scheme %d", scheme);
+    if (!c->have_particles_lists) return fail(PSM_ESTATE, "no valid particle set");
+    IntParams ip;
+    ip.boxes = c->d_boxes;
+    ip.part_box = c->d_partbox;
+    ip.P = c->P;
+    ip.P_total = c->P_total;
+    ip.dt = dt;
+    HIP_TRY(launch_integrate(scheme == PSM_EULER ? SCHEME_EULER : SCHEME_VERLET, ip, c->stream));
+    // the host copies of positions are stale from here on
+    for (auto& v : c->last_xr) v.clear();
+    return rebuild_lists_async(c);
+}
+
+extern "C" int psm_get_particles(psm_ctx* c, int box, double* x, double* U, double* omega) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    int n = c->np[box];
+    if (n == 0) return PSM_OK;
+    if (!x && !U && !omega) return PSM_OK;
+    size_t P1 = (size_t)std::max(c->P_total, 1);
+    int pb = c->box[box].part_base;
+    // columns x y z (0-2), ux uy uz (5-7), ox oy oz (8-10) of the device table
+    double* st = c->h_read;
+    HIP_TRY(hipMemcpy2DAsync(st, sizeof(double) * n, c->P.x + pb, sizeof(double) * P1, sizeof(double) * n, 3,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpy2DAsync(st + 3 * (size_t)n, sizeof(double) * n, c->P.ux + pb, sizeof(double) * P1,
+                             sizeof(double) * n, 6, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    rc = device_errors(c);
+    if (rc) return rc;
+    double* outs[3] = {x, U, omega};
+    for (int k = 0; k < 3; ++k) {
+        if (!outs[k]) continue;
+        for (int p = 0; p < n; ++p)
+            for (int a = 0; a < 3; ++a) outs[k][3 * p + a] = st[(size_t)(3 * k + a) * n + p];
+    }
     return PSM_OK;
 }
 

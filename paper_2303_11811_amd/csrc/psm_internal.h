@@ -46,12 +46,18 @@ struct BoxDev {
     double L[3], halfL[3];          // box lengths and their halves
     double sub_off[16];             // (k + 1/2)/nsub - 1/2, k < nsub
     double reach;                   // sqrt(3) (1/2 - 1/(2 nsub)) + 1e-9
+    // Sphere dynamics of the box: density ratio to the fluid and external
+    // acceleration (gravity minus buoyancy) used by the integrator.
+    double rho_p;
+    double accel[3];
 };
 
 // Global particle table, SoA, indexed by global particle id.
 struct Particles {
     double *x, *y, *z, *r, *fr, *ux, *uy, *uz, *ox, *oy, *oz;
-    double* acc;   // [P][6]: F (3), T (3) of the last step
+    double* acc;     // [P][6]: F (3), T (3) of the last step
+    double* fprev;   // [P][6]: total force and torque of the previous integration (velocity Verlet)
+    int* prev_ok;    // [P]: 1 once fprev holds a value
 };
 
 struct TileShape {
@@ -242,6 +248,17 @@ struct BinParams {
     int P_total;
     int T_total;
     TileShape ts;
+    long long cap;              // entries tile_pid holds
+};
+
+// Sphere integration (explicit Euler or velocity Verlet) of every particle.
+enum { SCHEME_EULER = 0, SCHEME_VERLET = 1 };
+struct IntParams {
+    const BoxDev* boxes;
+    const int* part_box;
+    Particles P;
+    int P_total;
+    double dt;
 };
 
 hipError_t launch_step(int storage, int map, bool filt, const StepParams& kp, int grid, hipStream_t st);
@@ -264,5 +281,9 @@ int stats_blocks();
 hipError_t launch_stats(int storage, const BoxDev& bx, int parity, float inv, double* part, double* out,
                         hipStream_t st);
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
+hipError_t launch_integrate(int scheme, const IntParams& ip, hipStream_t st);
+// err |= 1 if the lists need more than cap entries, |= 2 if a tile lists more than MAXC spheres
+hipError_t launch_check_lists(const int* stats, long long cap, int* err, hipStream_t st);
+hipError_t launch_fill_int(int* a, long long n, int v, hipStream_t st);
 
 }  // namespace psm

@@ -172,11 +172,6 @@ __device__ __forceinline__ void particle_velocity(int c, double dx, double dy, d
 #ifndef PSM_WAVES_PER_EU_F32
 #define PSM_WAVES_PER_EU_F32 4
 #endif
-// 1: the values of the next z cell are loaded before the current cell is
-// collided, so a wave keeps 19 loads in flight during its arithmetic.
-#ifndef PSM_PREFETCH
-#define PSM_PREFETCH 0
-#endif
 
 // pull of the 19 values of one cell: planes z (bz), z-1 (bm), z+1 (bp)
 #define PSM_LOAD19(F, bz, bm, bp)                      \
@@ -251,7 +246,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
         const int tcy = (lt / ntx) % nty;
         const int tcz = lt / (ntx * nty);
         const int e0 = tile_off[t];
-        const int nc = tile_off[t + 1] - e0;
+        const int nc = tile_off[t + 1] - e0;   // at most MAXC: the scan caps every list
 
         if (nc > 0) {
             for (int c = tid; c < nc; c += WG) {
@@ -325,15 +320,6 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
         }
 
         constexpr int QB = BLK * (int)sizeof(T);
-        const GCHAR* const src_c = (const GCHAR*)src;
-        auto plane = [&](int zz) -> const GCHAR* {
-            return src_c + (zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz)) * pbytes;
-        };
-        R fnext[NQ];
-        if (PSM_PREFETCH) {
-            const int z0 = tcz * TZ;
-            if (lane_ok && z0 < nz) PSM_LOAD19(fnext, plane(z0), plane(z0 - 1), plane(z0 + 1));
-        }
 
         for (int k = 0; k < TZ; ++k) {
             const int z = tcz * TZ + k;
@@ -391,13 +377,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
             R hx = 0, hy = 0, hz = 0;   // 2 j - U, for the force of eq. (21)
             if (lane_ok) {
                 R f[NQ];
-                if (PSM_PREFETCH) {
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q) f[q] = fnext[q];
-                    if (k + 1 < TZ && z + 1 < nz) PSM_LOAD19(fnext, sbp, sbz, plane(z + 2));
-                } else {
-                    PSM_LOAD19(f, sbz, sbm, sbp);
-                }
+                PSM_LOAD19(f, sbz, sbm, sbp);
 
                 // 3. moments, eqs. (6)-(7); U carries the f/2 shift
                 R rho = ((((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) +
@@ -592,8 +572,11 @@ __global__ __launch_bounds__(256) void k_bin(BinParams bp) {
         if (!FILL) {
             atomicAdd(&bp.tile_cnt[t], 1);
         } else {
+            // a list holds at most MAXC spheres (the scan caps it; the excess
+            // is flagged from the uncapped maximum)
             int pos = atomicSub(&bp.tile_cnt[t], 1) - 1;
-            bp.tile_pid[bp.tile_off[t] + pos] = p;
+            long long e = (long long)bp.tile_off[t] + pos;
+            if (pos < MAXC && e < bp.cap) bp.tile_pid[e] = p;
         }
     }
 }
@@ -606,8 +589,8 @@ __global__ void k_fill_int(int* a, long long n, int v) {
 
 // Exclusive scan of cnt[0..n) into off[0..n] in three passes over chunks of
 // SCAN_CHUNK counts: chunk sums and maxima, a one-workgroup scan of the chunk
-// sums, then each chunk scanned with its offset. stats[0] = largest count,
-// stats[1] = total.
+// sums, then each chunk scanned with its offset. Every list length is capped
+// at MAXC; stats[0] = largest uncapped count, stats[1] = total of the lists.
 constexpr int SCAN_CHUNK = 1024;
 
 __device__ inline int block_incl_scan_256(int v, int* sh) {
@@ -633,8 +616,8 @@ __global__ __launch_bounds__(256) void k_scan_chunks(const int* cnt, int n, int*
     for (int k = 0; k < SCAN_CHUNK / 256; ++k) {
         int i = base + k * 256 + tid;
         int v = i < n ? cnt[i] : 0;
-        sum += v;
-        mx = v > mx ? v : mx;
+        sum += v < MAXC ? v : MAXC;   // list lengths are capped at MAXC
+        mx = v > mx ? v : mx;         // the uncapped maximum reports an excess
     }
     s_sum[tid] = sum;
     s_max[tid] = mx;
@@ -686,7 +669,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const int* cnt, int n, const
     int v[4], loc = 0;
     for (int k = 0; k < 4; ++k) {
         int i = base + tid * 4 + k;
-        v[k] = i < n ? cnt[i] : 0;
+        v[k] = i < n ? (cnt[i] < MAXC ? cnt[i] : MAXC) : 0;
         loc += v[k];
     }
     int inc = block_incl_scan_256(loc, sh);
@@ -890,6 +873,71 @@ __global__ __launch_bounds__(256) void k_stream_copy(const double2* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Sphere integration (Sec. 2.2.2) for collision-free spheres, one thread per
+// particle slot. m = rho_p (4/3) pi r^3, I = (2/5) m r^2; the total force is
+// the hydrodynamic force of the last step plus m times the box's external
+// acceleration, the torque is the hydrodynamic torque.
+//   Euler:  x += dt U;  U += dt F/m;  Om += dt T/I.
+//   Verlet (eqs. 15-16), once after each fluid step: complete the velocity
+//   with the previous and the new force (skipped until a previous force
+//   exists), then advance the position with the new one.
+// Positions are wrapped into [0, L). No fused multiply-add, so that the
+// update is reproducible bit for bit.
+template <int SCHEME>
+__global__ __launch_bounds__(256) void k_integrate(IntParams ip) {
+#pragma clang fp contract(off)
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= ip.P_total) return;
+    const BoxDev& bx = ip.boxes[ip.part_box[p]];
+    if (p - bx.part_base >= bx.np) return;
+    const double pi = 3.14159265358979323846;
+    const double dt = ip.dt, r = ip.P.r[p];
+    const double m = bx.rho_p * (4.0 / 3.0) * pi * r * r * r;
+    const double inertia = 0.4 * m * r * r;
+    double* pos[3] = {ip.P.x, ip.P.y, ip.P.z};
+    double* vel[3] = {ip.P.ux, ip.P.uy, ip.P.uz};
+    double* ang[3] = {ip.P.ox, ip.P.oy, ip.P.oz};
+    const double* acc = ip.P.acc + 6LL * p;
+    double* fp = ip.P.fprev + 6LL * p;
+    const bool prev = SCHEME == SCHEME_VERLET && ip.P.prev_ok[p] != 0;
+    for (int a = 0; a < 3; ++a) {
+        const double F = acc[a] + m * bx.accel[a];
+        const double T = acc[3 + a];
+        double x = pos[a][p], U = vel[a][p], W = ang[a][p];
+        if (SCHEME == SCHEME_EULER) {
+            x = x + dt * U;
+            U = U + dt * F / m;
+            W = W + dt * T / inertia;
+        } else {
+            if (prev) {
+                U = U + dt / (2.0 * m) * (fp[a] + F);
+                W = W + dt / (2.0 * inertia) * (fp[3 + a] + T);
+            }
+            x = x + (dt * U + dt * dt / (2.0 * m) * F);
+            fp[a] = F;
+            fp[3 + a] = T;
+        }
+        const double L = bx.L[a];
+        double w = x - L * floor(x / L);
+        if (w >= L) w -= L;
+        if (w < 0.0) w = 0.0;
+        pos[a][p] = w;
+        vel[a][p] = U;
+        ang[a][p] = W;
+    }
+    if (SCHEME == SCHEME_VERLET) ip.P.prev_ok[p] = 1;
+}
+
+__global__ void k_check_lists(const int* __restrict__ stats, long long cap, int* __restrict__ err) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int e = 0;
+        if ((long long)stats[1] > cap) e |= 1;
+        if (stats[0] > MAXC) e |= 2;
+        if (e) err[0] |= e;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers (called by the engine).
 
 static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -1024,6 +1072,27 @@ hipError_t launch_stats(int storage, const BoxDev& bx, int parity, float inv, do
         default: hipLaunchKernelGGL(k_stats_partial<St16>, dim3(nb), dim3(256), 0, st, bx, parity, inv, part); break;
     }
     hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, st, part, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate(int scheme, const IntParams& ip, hipStream_t st) {
+    if (ip.P_total == 0) return hipSuccess;
+    if (scheme == SCHEME_EULER)
+        hipLaunchKernelGGL(k_integrate<SCHEME_EULER>, dim3(blocks_for(ip.P_total, 256)), dim3(256), 0, st, ip);
+    else
+        hipLaunchKernelGGL(k_integrate<SCHEME_VERLET>, dim3(blocks_for(ip.P_total, 256)), dim3(256), 0, st, ip);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_lists(const int* stats, long long cap, int* err, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_lists, dim3(1), dim3(64), 0, st, stats, cap, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* a, long long n, int v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    unsigned nb = blocks_for(n, 256);
+    hipLaunchKernelGGL(k_fill_int, dim3(nb > 4096 ? 4096 : nb), dim3(256), 0, st, a, n, v);
     return hipGetLastError();
 }
 

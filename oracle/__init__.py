@@ -46,7 +46,8 @@ def build(force: bool = True) -> str:
 class _Box(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("tau", ctypes.c_double), ("fext", ctypes.c_double * 3),
-                ("mapping", ctypes.c_int), ("nsub", ctypes.c_int), ("walls_z", ctypes.c_int)]
+                ("mapping", ctypes.c_int), ("nsub", ctypes.c_int), ("walls_z", ctypes.c_int),
+                ("uwall", (ctypes.c_double * 3) * 2)]
 
 
 _lib = None
@@ -100,16 +101,19 @@ def _f64(a, shape=None):
 
 
 class Box:
-    """A periodic box (optionally with test-only z walls)."""
+    """A box, periodic in x and y; in z periodic, or bounded by half-way
+    bounce-back walls at z = -1/2 and z = nz - 1/2 (cell-index coordinates)
+    moving with wall_u[0] (bottom) and wall_u[1] (top)."""
 
     def __init__(self, nx, ny, nz, tau, fext=(0.0, 0.0, 0.0), mapping=MAP_LINEAR, nsub=4,
-                 walls_z=False):
+                 walls_z=False, wall_u=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.tau = float(tau)
         self.fext = tuple(float(v) for v in fext)
         self.mapping = int(mapping)
         self.nsub = int(nsub)
         self.walls_z = bool(walls_z)
+        self.wall_u = tuple(tuple(float(v) for v in w) for w in wall_u)
 
     @property
     def N(self):
@@ -122,6 +126,9 @@ class Box:
         for a in range(3):
             b.fext[a] = self.fext[a]
         b.mapping, b.nsub, b.walls_z = self.mapping, self.nsub, int(self.walls_z)
+        for w in range(2):
+            for a in range(3):
+                b.uwall[w][a] = self.wall_u[w][a]
         return b
 
 

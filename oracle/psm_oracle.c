@@ -37,8 +37,11 @@
  *   - Sub-division sampling (named in Sec. 2.3.2 as the alternative to the
  *     linear approximation): N^3 points at offsets (k+1/2)/N - 1/2 per axis,
  *     inclusion |s| <= r, evaluated without fused multiply-add.
- *   - Test-only half-way bounce-back walls at z = -1/2 and z = nz - 1/2 for the
- *     Poiseuille check (not part of the engine).
+ *   - No-slip walls (the paper's fluidized bed has them, Sec. 4; it does not
+ *     name the scheme): half-way bounce-back at z = -1/2 and z = nz - 1/2 in
+ *     cell-index coordinates, with the moving-wall term of Ladd for a wall
+ *     velocity u_w (fluid density 1): a population f~_q leaving the fluid
+ *     through the wall returns as f_qbar = f~_q - 6 w_q (c_q . u_w).
  *
  * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared -o libpsm_oracle.so
  */
@@ -78,7 +81,8 @@ typedef struct {
     double fext[3];
     int mapping;   /* 0: linear approximation, 1: sub-division sampling */
     int nsub;      /* samples per axis for mapping == 1 */
-    int walls_z;   /* test mode: half-way bounce-back walls in z */
+    int walls_z;   /* half-way bounce-back walls at z = -1/2 and z = nz - 1/2 */
+    double uwall[2][3];   /* velocities of the bottom and the top wall */
 } psmo_box;
 
 typedef struct {
@@ -468,8 +472,10 @@ long long psmo_run(const psmo_box *b, int nsteps, int np, const double *x, const
                     for (int q = 0; q < NQ; ++q) {
                         int ii = i + CQ[q][0], jj = j + CQ[q][1], kk = k + CQ[q][2];
                         if (b->walls_z && (kk < 0 || kk >= nz)) {
-                            /* half-way bounce-back at a resting wall (test mode) */
-                            fnew[inverse_dir(q) * N + n] = ft[q];
+                            /* half-way bounce-back, moving-wall term for the wall crossed */
+                            const double *uw = b->uwall[kk < 0 ? 0 : 1];
+                            double cu = CQ[q][0] * uw[0] + CQ[q][1] * uw[1] + CQ[q][2] * uw[2];
+                            fnew[inverse_dir(q) * N + n] = ft[q] - 6.0 * WQ[q] * cu;
                             continue;
                         }
                         ii = wrap_index(ii, nx);

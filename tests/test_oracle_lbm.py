@@ -192,3 +192,26 @@ def test_no_particles_equals_textbook_lbm():
         ref = _textbook_lbm_step(ref, dims, tau, g)
     got = oracle.run(box, f, 5).f
     assert np.max(np.abs(got - ref)) < 1e-15
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.9, 1.4])
+def test_couette_moving_walls_linear_profile(tau):
+    """Walls at z = -1/2 and z = H - 1/2 moving with U_b and U_t along x and y:
+    the steady BGK solution with half-way bounce-back and the moving-wall term
+    is exactly linear, u(k) = U_b + (U_t - U_b)(k + 1/2)/H, at any tau."""
+    H = 10
+    Ub, Ut = np.array([-0.01, 0.004, 0.0]), np.array([0.03, -0.006, 0.0])
+    box = oracle.Box(2, 2, H, tau=tau, walls_z=True, wall_u=(Ub, Ut))
+    f = oracle.equilibrium(box, np.zeros((3, box.N)))
+    nu = (tau - 0.5) / 3.0
+    nsteps = int(50 * H * H / (math.pi ** 2 * nu)) + 200
+    f = oracle.run(box, f, nsteps).f
+    rho, u = oracle.macroscopic(box, f)
+    k = np.arange(H) + 0.0
+    for a in range(2):
+        exact = Ub[a] + (Ut[a] - Ub[a]) * (k + 0.5) / H
+        prof = u[a].reshape(H, 2, 2)[:, 0, 0]
+        assert np.max(np.abs(prof - exact)) < 1e-10 * np.abs(Ut - Ub).max()
+    assert np.max(np.abs(u[2])) < 1e-14
+    # tangential walls neither add nor remove mass
+    assert abs(rho.sum() - box.N) < 1e-11 * box.N

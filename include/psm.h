@@ -17,7 +17,8 @@
  *   throws. psm_last_error() returns a thread-local text of the last failure.
  * - Argument checks happen on the host before anything is enqueued; a bad
  *   argument returns PSM_EINVAL and leaves the context unchanged.
- * - Lattice units: dx = dt = 1, rho_0 = 1, c_s^2 = 1/3. All boxes are periodic.
+ * - Lattice units: dx = dt = 1, rho_0 = 1, c_s^2 = 1/3. Boxes are periodic in
+ *   x and y, and in z unless they have walls (psm_box_desc.walls_z).
  * - Cells: index n = x + nx*(y + ny*z); cell (i,j,k) has its centre at
  *   (i+1/2, j+1/2, k+1/2) in [0,nx) x [0,ny) x [0,nz).
  * - PDFs: canonical layout [19][N] (q-major), FP64, pre-collision state
@@ -69,6 +70,10 @@ typedef struct psm_box_desc {
     double max_radius;      /* largest sphere radius that will be set (>= 1) */
     int mapping;            /* psm_mapping */
     int subsample_n;        /* samples per axis for PSM_MAP_SUBSAMPLE (1..16) */
+    int walls_z;            /* 0: periodic in z; 1: no-slip walls at z = 0 and z = nz (cell faces),
+                               half-way bounce-back with the moving-wall term 6 w_q (c_q . u_w) */
+    double wall_u[2][3];    /* velocities of the z = 0 and z = nz walls (walls_z = 1); a normal
+                               component moves mass through the wall */
 } psm_box_desc;
 
 typedef struct psm_ctx psm_ctx;
@@ -112,7 +117,8 @@ int psm_get_macroscopic(psm_ctx* ctx, int box, double* rho, double* u);
 /* Set the spheres of box `box` (Sec. 3.1.1: positions, radii, then linear and
  * angular velocities). Host arrays, row-major: x (n,3), r (n), U (n,3),
  * omega (n,3) (NULL omega = 0); they are copied before the call returns.
- * Positions are wrapped into the box. Radii must lie in [1, max_radius]. The
+ * Positions are wrapped into the box. Radii must lie in [1, max_radius]; in a
+ * box with walls every centre needs r + 1 <= z <= nz - r - 1. The
  * library computes f(r) of eq. (26) in FP64 and uploads through pinned staging
  * (asynchronous). When positions or radii differ from the previous call it
  * rebuilds the per-tile candidate lists, which synchronises and returns

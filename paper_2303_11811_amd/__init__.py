@@ -36,7 +36,8 @@ class psm_box_desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("tau", ctypes.c_double), ("fext", ctypes.c_double * 3),
                 ("max_particles", ctypes.c_int), ("max_radius", ctypes.c_double),
-                ("mapping", ctypes.c_int), ("subsample_n", ctypes.c_int)]
+                ("mapping", ctypes.c_int), ("subsample_n", ctypes.c_int),
+                ("walls_z", ctypes.c_int), ("wall_u", (ctypes.c_double * 3) * 2)]
 
 
 _lib = None
@@ -106,7 +107,8 @@ def _dptr(a):
 
 
 def make_desc(nx, ny, nz, tau, fext=(0.0, 0.0, 0.0), max_particles=0, max_radius=1.0,
-              mapping=PSM_MAP_LINEAR, subsample_n=4) -> psm_box_desc:
+              mapping=PSM_MAP_LINEAR, subsample_n=4, walls_z=False,
+              wall_u=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))) -> psm_box_desc:
     d = psm_box_desc()
     d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
     d.tau = float(tau)
@@ -116,6 +118,10 @@ def make_desc(nx, ny, nz, tau, fext=(0.0, 0.0, 0.0), max_particles=0, max_radius
     d.max_radius = float(max_radius)
     d.mapping = int(mapping)
     d.subsample_n = int(subsample_n)
+    d.walls_z = int(bool(walls_z))
+    for w in range(2):
+        for a in range(3):
+            d.wall_u[w][a] = float(wall_u[w][a])
     return d
 
 
@@ -407,4 +413,4 @@ def desc_from_spec(spec, max_particles=None, max_radius=None):
     n = spec.n_particles if max_particles is None else max_particles
     rmax = (float(np.max(spec.r)) if len(spec.r) else 1.0) if max_radius is None else max_radius
     return make_desc(*spec.dims, spec.tau, spec.fext, max_particles=n, max_radius=max(rmax, 1.0),
-                     mapping=spec.mapping, subsample_n=spec.nsub)
+                     mapping=spec.mapping, subsample_n=spec.nsub, walls_z=spec.walls_z, wall_u=spec.wall_u)

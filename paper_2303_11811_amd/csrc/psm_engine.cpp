@@ -101,6 +101,11 @@ static int validate(const psm_box_desc* boxes, int nbox, int storage) {
         for (int a = 0; a < 3; ++a)
             if (!std::isfinite(d.fext[a])) return fail(PSM_EINVAL, "box %d: non-finite body force", b);
         if (d.max_particles < 0) return fail(PSM_EINVAL, "box %d: max_particles < 0", b);
+        if (d.walls_z != 0 && d.walls_z != 1) return fail(PSM_EINVAL, "box %d: walls_z must be 0 or 1", b);
+        for (int w = 0; w < 2; ++w)
+            for (int a = 0; a < 3; ++a)
+                if (d.walls_z && !std::isfinite(d.wall_u[w][a]))
+                    return fail(PSM_EINVAL, "box %d: non-finite wall velocity", b);
         if (d.mapping != PSM_MAP_LINEAR && d.mapping != PSM_MAP_SUBSAMPLE)
             return fail(PSM_EINVAL, "box %d: unknown mapping %d", b, d.mapping);
         if (d.mapping == PSM_MAP_SUBSAMPLE && (d.subsample_n < 1 || d.subsample_n > 16))
@@ -414,6 +419,14 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
         for (int k = 0; k < 16; ++k) bx.sub_off[k] = k < bx.nsub ? (k + 0.5) / bx.nsub - 0.5 : 0.0;
         bx.reach = 0.8660254037844386 * (1.0 - 1.0 / bx.nsub) + 1e-9;
         bx.rho_p = 1.0;
+        bx.walls = d.walls_z;
+        for (int w = 0; w < 2; ++w)
+            for (int q = 0; q < NQ; ++q) {
+                // entering through the bottom wall: c_z = +1; through the top: c_z = -1
+                bool in = d.walls_z && CZ[q] == (w == 0 ? 1 : -1);
+                double cu = CX[q] * d.wall_u[w][0] + CY[q] * d.wall_u[w][1] + CZ[q] * d.wall_u[w][2];
+                bx.bw[w][q] = in ? 6.0 * wq(q) * cu : 0.0;
+            }
         bx.pw[0] = bx.pref * W0;
         bx.pw[1] = bx.pref * W1;
         bx.pw[2] = bx.pref * W2;
@@ -566,6 +579,8 @@ extern "C" int psm_set_particles(psm_ctx* c, int box, int n, const double* x, co
     for (int p = 0; p < n; ++p) {
         if (!(r[p] >= 1.0 && r[p] <= d.max_radius))
             return fail(PSM_EINVAL, "particle %d: radius %g outside [1, %g]", p, r[p], d.max_radius);
+        if (d.walls_z && !(x[3 * p + 2] >= r[p] + 1.0 && x[3 * p + 2] <= d.nz - r[p] - 1.0))
+            return fail(PSM_EINVAL, "particle %d: centre closer than r + 1 to a wall", p);
         for (int a = 0; a < 3; ++a) {
             if (!std::isfinite(x[3 * p + a]) || !std::isfinite(U[3 * p + a]) ||
                 (omega && !std::isfinite(omega[3 * p + a])))

@@ -50,7 +50,15 @@ struct BoxDev {
     // acceleration (gravity minus buoyancy) used by the integrator.
     double rho_p;
     double accel[3];
+    // No-slip walls at z = 0 and z = nz (half-way bounce-back). A population
+    // q entering a boundary cell through wall w is the one the cell sent
+    // against the wall (direction opp(q)) plus bw[w][q] = 6 w_q (c_q . u_w).
+    int walls;
+    double bw[2][NQ];
 };
+
+// Opposite direction: the pairs (1,2), (3,4), ..., (17,18) are opposite.
+__host__ __device__ constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
 
 // Global particle table, SoA, indexed by global particle id.
 struct Particles {

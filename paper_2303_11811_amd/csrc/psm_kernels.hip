@@ -378,6 +378,25 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
             if (lane_ok) {
                 R f[NQ];
                 PSM_LOAD19(f, sbz, sbm, sbp);
+                if (bx.walls) {
+                    // through a wall: the population this cell sent against it
+                    // last step, plus the moving-wall term (uniform branches)
+                    const R ws = S::SCALED ? sc : (R)1;
+                    if (z == 0) {
+                        f[5] = S::loadb(sbz + 6 * QB, o00, kp.h_inv) + ws * (R)bx.bw[0][5];
+                        f[11] = S::loadb(sbz + 12 * QB, o00, kp.h_inv) + ws * (R)bx.bw[0][11];
+                        f[14] = S::loadb(sbz + 13 * QB, o00, kp.h_inv) + ws * (R)bx.bw[0][14];
+                        f[15] = S::loadb(sbz + 16 * QB, o00, kp.h_inv) + ws * (R)bx.bw[0][15];
+                        f[18] = S::loadb(sbz + 17 * QB, o00, kp.h_inv) + ws * (R)bx.bw[0][18];
+                    }
+                    if (z == nz - 1) {
+                        f[6] = S::loadb(sbz + 5 * QB, o00, kp.h_inv) + ws * (R)bx.bw[1][6];
+                        f[12] = S::loadb(sbz + 11 * QB, o00, kp.h_inv) + ws * (R)bx.bw[1][12];
+                        f[13] = S::loadb(sbz + 14 * QB, o00, kp.h_inv) + ws * (R)bx.bw[1][13];
+                        f[16] = S::loadb(sbz + 15 * QB, o00, kp.h_inv) + ws * (R)bx.bw[1][16];
+                        f[17] = S::loadb(sbz + 18 * QB, o00, kp.h_inv) + ws * (R)bx.bw[1][17];
+                    }
+                }
 
                 // 3. moments, eqs. (6)-(7); U carries the f/2 shift
                 R rho = ((((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) +
@@ -685,6 +704,42 @@ __global__ __launch_bounds__(256) void k_scan_apply(const int* cnt, int n, const
 // ---------------------------------------------------------------------------
 // State I/O. Canonical f(x,t) = grid[q][x - c_q] (pull storage).
 
+// Canonical f_q(x, t) of cell (x, y, z) from the stored (pulled) layout, in
+// the units of S::to_f64 (the deviation for the deviation forms): the value
+// streamed from x - c_q, or, through a wall, the population the cell sent
+// against it (direction opp(q)) plus the moving-wall term.
+template <class S>
+__device__ inline double pull_value(const BoxDev& bx, const typename S::T* g, int q, int x, int y, int z, float inv) {
+    int zs = z - CZ[q];
+    if (bx.walls && (zs < 0 || zs >= bx.nz))
+        return S::to_f64(g[pdf_index(bx, opp(q), x, y, z)], inv) + bx.bw[zs < 0 ? 0 : 1][q];
+    int xs = x - CX[q], ys = y - CY[q];
+    xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
+    ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
+    zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
+    return S::to_f64(g[pdf_index(bx, q, xs, ys, zs)], inv);
+}
+
+// Inverse of pull_value for the stored slot (q, x, y, z): the cell that will
+// read it, and the direction and wall term it reads it with. Returns the
+// reading cell index; *dir and *add describe the canonical value to store:
+// slot = f_dir(cell) - add.
+__device__ inline long long slot_reader(const BoxDev& bx, int q, int x, int y, int z, int* dir, double* add) {
+    int zd = z + CZ[q];
+    if (bx.walls && (zd < 0 || zd >= bx.nz)) {
+        *dir = opp(q);
+        *add = bx.bw[zd < 0 ? 0 : 1][opp(q)];
+        return x + (long long)bx.nx * (y + (long long)bx.ny * z);
+    }
+    int xd = x + CX[q], yd = y + CY[q];
+    xd = xd < 0 ? xd + bx.nx : (xd >= bx.nx ? xd - bx.nx : xd);
+    yd = yd < 0 ? yd + bx.ny : (yd >= bx.ny ? yd - bx.ny : yd);
+    zd = zd < 0 ? zd + bx.nz : (zd >= bx.nz ? zd - bx.nz : zd);
+    *dir = q;
+    *add = 0.0;
+    return xd + (long long)bx.nx * (yd + (long long)bx.ny * zd);
+}
+
 template <class S>
 __global__ void k_set_pdfs(BoxDev bx, int parity, const double* __restrict__ f, float scale) {
     long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -693,11 +748,10 @@ __global__ void k_set_pdfs(BoxDev bx, int parity, const double* __restrict__ f, 
     typename S::T* g = (typename S::T*)bx.grid[parity];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        int xs = x + CX[q], ys = y + CY[q], zs = z + CZ[q];
-        xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
-        ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
-        zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
-        double v = f[(long long)q * bx.N + xs + (long long)bx.nx * (ys + (long long)bx.ny * zs)];
+        int dq;
+        double add;
+        long long s = slot_reader(bx, q, x, y, z, &dq, &add);
+        double v = f[(long long)dq * bx.N + s] - add;
         if (S::DEV) v -= wq(q);
         g[pdf_index(bx, q, x, y, z)] = S::from_f64(v, scale);
     }
@@ -712,17 +766,15 @@ __global__ void k_set_equilibrium(BoxDev bx, int parity, const double* __restric
     typename S::T* g = (typename S::T*)bx.grid[parity];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        int xs = x + CX[q], ys = y + CY[q], zs = z + CZ[q];
-        xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
-        ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
-        zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
-        long long s = xs + (long long)bx.nx * (ys + (long long)bx.ny * zs);
+        int dq;
+        double add;
+        long long s = slot_reader(bx, q, x, y, z, &dq, &add);
         double r = rho ? rho[s] : 1.0;
         double vx = u[s], vy = u[bx.N + s], vz = u[2LL * bx.N + s];
-        double cv = CX[q] * vx + CY[q] * vy + CZ[q] * vz;
+        double cv = CX[dq] * vx + CY[dq] * vy + CZ[dq] * vz;
         double vv = vx * vx + vy * vy + vz * vz;
-        double rr = S::DEV ? r - 1.0 : r;   // deviation form: E_q - w_q
-        double e = wq(q) * (rr + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
+        double rr = S::DEV ? r - 1.0 : r;   // deviation form: E_q - w_q (w_q = w_opp(q))
+        double e = wq(dq) * (rr + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv) - add;
         g[pdf_index(bx, q, x, y, z)] = S::from_f64(e, scale);
     }
 }
@@ -735,11 +787,7 @@ __global__ void k_get_pdfs(BoxDev bx, int parity, double* __restrict__ f, float 
     const typename S::T* g = (const typename S::T*)bx.grid[parity];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        int xs = x - CX[q], ys = y - CY[q], zs = z - CZ[q];
-        xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
-        ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
-        zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
-        double v = S::to_f64(g[pdf_index(bx, q, xs, ys, zs)], inv);
+        double v = pull_value<S>(bx, g, q, x, y, z, inv);
         if (S::DEV) v += wq(q);
         f[(long long)q * bx.N + n] = v;
     }
@@ -755,11 +803,7 @@ __global__ void k_get_pdfs_at(BoxDev bx, int parity, const int* __restrict__ cel
     const typename S::T* g = (const typename S::T*)bx.grid[parity];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        int xs = x - CX[q], ys = y - CY[q], zs = z - CZ[q];
-        xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
-        ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
-        zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
-        double v = S::to_f64(g[pdf_index(bx, q, xs, ys, zs)], inv);
+        double v = pull_value<S>(bx, g, q, x, y, z, inv);
         if (S::DEV) v += wq(q);
         out[(long long)q * ncells + i] = v;
     }
@@ -775,11 +819,7 @@ __global__ void k_macroscopic(BoxDev bx, int parity, double* __restrict__ rho, d
     double r = 0, j[3] = {0, 0, 0};
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        int xs = x - CX[q], ys = y - CY[q], zs = z - CZ[q];
-        xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
-        ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
-        zs = zs < 0 ? zs + bx.nz : (zs >= bx.nz ? zs - bx.nz : zs);
-        double v = S::to_f64(g[pdf_index(bx, q, xs, ys, zs)], inv);
+        double v = pull_value<S>(bx, g, q, x, y, z, inv);
         if (S::DEV) v += wq(q);
         r += v;
         j[0] += v * CX[q]; j[1] += v * CY[q]; j[2] += v * CZ[q];
@@ -823,7 +863,7 @@ __global__ void k_map_dense(BoxDev bx, int box_tile_base_unused, Particles P, co
     if (sl.dropped) atomicAdd(dropped, (unsigned long long)sl.dropped);
 }
 
-// FP64 mass and momentum of the stored state (a permutation of f(x,t)):
+// FP64 mass and momentum of the stored state (each slot is one f_q(x,t)):
 // per-block partial sums, then one block adds them in a fixed order.
 template <class S>
 __global__ __launch_bounds__(256) void k_stats_partial(BoxDev bx, int parity, float inv, double* __restrict__ part) {
@@ -835,10 +875,14 @@ __global__ __launch_bounds__(256) void k_stats_partial(BoxDev bx, int parity, fl
         int x = n % bx.nx, y = (n / bx.nx) % bx.ny, z = n / ((long long)bx.nx * bx.ny);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            double v = S::to_f64(g[pdf_index(bx, q, x, y, z)], inv);
+            // the slot holds f_dq(reader) - add (a permutation of f(x,t) without walls)
+            int dq;
+            double add;
+            (void)slot_reader(bx, q, x, y, z, &dq, &add);
+            double v = S::to_f64(g[pdf_index(bx, q, x, y, z)], inv) + add;
             if (S::DEV) v += wq(q);
             m += v;
-            px += v * CX[q]; py += v * CY[q]; pz += v * CZ[q];
+            px += v * CX[dq]; py += v * CY[dq]; pz += v * CZ[dq];
         }
     }
     s[0][threadIdx.x] = m; s[1][threadIdx.x] = px; s[2][threadIdx.x] = py; s[3][threadIdx.x] = pz;

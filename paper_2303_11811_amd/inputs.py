@@ -183,7 +183,7 @@ def shear_wave(dims, amp, axis_u=0, axis_k=1):
 
 @dataclass
 class BoxSpec:
-    """One periodic box and its particles."""
+    """One box (periodic, or with walls in z) and its particles."""
     dims: tuple
     tau: float
     fext: tuple = (0.0, 0.0, 0.0)
@@ -195,6 +195,8 @@ class BoxSpec:
     Om: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
     u0: np.ndarray | None = None   # initial velocity [3][N]; None = rest
     rho0: np.ndarray | None = None
+    walls_z: bool = False          # no-slip walls at z = 0 and z = nz instead of periodicity
+    wall_u: tuple = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))   # bottom and top wall velocities
 
     @property
     def N(self):

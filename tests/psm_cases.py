@@ -8,9 +8,9 @@ import oracle
 import paper_2303_11811_amd as psm
 
 
-def oracle_box(spec, walls_z=False):
+def oracle_box(spec):
     return oracle.Box(*spec.dims, tau=spec.tau, fext=spec.fext, mapping=spec.mapping, nsub=spec.nsub,
-                      walls_z=walls_z)
+                      walls_z=spec.walls_z, wall_u=spec.wall_u)
 
 
 def initial_f(spec):

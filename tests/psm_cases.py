@@ -66,3 +66,75 @@ def assert_forces_close(F_gpu, F_ref, A, lever=1.0, rtol=1e-12, atol_scale=1e-14
     d = np.linalg.norm(F_gpu - F_ref, axis=1)
     bound = rtol * np.linalg.norm(F_ref, axis=1) + atol_scale * A * lever + 1e-300
     assert np.all(d <= bound), f"max excess {np.max(d / bound):.3g}"
+
+
+CX = np.array([0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0])
+CY = np.array([0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1])
+CZ = np.array([0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1])
+W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def sample_cells(spec, x, r, rng, n_surface=32, n_random=32):
+    """Cells near sphere surfaces (where the PSM terms act) plus random cells."""
+    dims = np.asarray(spec.dims)
+    cells = []
+    if len(r):
+        for p in rng.integers(0, len(r), n_surface):
+            d = rng.normal(size=3)
+            d *= (r[p] + rng.uniform(-1.5, 0.8)) / np.linalg.norm(d)
+            cells.append(tuple((np.floor(x[p] + d).astype(int)) % dims))
+    cells += [tuple(v) for v in rng.integers(0, dims, (n_random, 3))]
+    return cells
+
+
+def _idx(c, dims):
+    return int(c[0] % dims[0] + dims[0] * ((c[1] % dims[1]) + dims[1] * (c[2] % dims[2])))
+
+
+def gather_sources(eng, box, spec, cells):
+    """The engine's f(t) at the 19 source cells x - c_q of every sampled cell."""
+    dims = spec.dims
+    flat = [(i - CX[q], j - CY[q], k - CZ[q]) for (i, j, k) in cells for q in range(19)]
+    f_t = eng.get_pdfs_at(box, [_idx(t, dims) for t in flat]).cpu().numpy()
+    return flat, f_t
+
+
+def oracle_after(eng, box, spec, cells, flat, f_t, x, r, U, Om):
+    """After one engine step: the engine's f(x, t+1) at the sampled cells and
+    the oracle's value computed in FP64 from the engine's f(t) at the sources
+    (map_cell over all spheres, collide_cell): arrays (ncells, 19) each."""
+    dims = spec.dims
+    got = eng.get_pdfs_at(box, [_idx(c, dims) for c in cells]).cpu().numpy().T.copy()
+    ob = oracle.Box(*dims, tau=spec.tau, fext=spec.fext, mapping=spec.mapping, nsub=spec.nsub)
+    frv = oracle.fr(r) if len(r) else np.zeros(0)
+    ref = np.zeros((len(cells), 19))
+    for a in range(len(cells)):
+        for q in range(19):
+            t = flat[a * 19 + q]
+            si, sj, sk = t[0] % dims[0], t[1] % dims[1], t[2] % dims[2]
+            ns, pid, B, _ = oracle.map_cell(ob, si, sj, sk, x, r, frv)
+            ft, _ = oracle.collide_cell(ob, si, sj, sk, f_t[:, a * 19 + q], pid[:ns], B[:ns], x, U, Om)
+            ref[a, q] = ft[q]
+    return got, ref
+
+
+def one_step_sampled(eng, box, spec, cells, x, r, U, Om):
+    """gather_sources, one engine step, oracle_after."""
+    flat, f_t = gather_sources(eng, box, spec, cells)
+    eng.step(1)
+    return oracle_after(eng, box, spec, cells, flat, f_t, x, r, U, Om)
+
+
+def deviation_bound(ref, storage):
+    """Per-value bound for one step computed in FP32 from the same state:
+    the rounding of the stored output (FP32: 2^-24 relative; FP16 keeps
+    2^10 d: 2^-11 relative, 2^-35 absolute below the normal range) plus
+    sixteen FP32 roundings at the largest deviation of the cell
+    (16 x 2^-24 < 1e-6)."""
+    d = np.abs(ref - W[None, :])
+    cell_max = d.max(axis=1, keepdims=True)
+    if storage == psm.PSM_FP16DEV:
+        out = 2.0 ** -11 * d + 2.0 ** -35
+    else:
+        out = 2.0 ** -24 * d
+    return out + 1e-6 * cell_max

@@ -1,0 +1,147 @@
+"""Full-size checks of the other benchmark workloads, in the launch the
+autotuner picks (as bench.py does): the FP32- and FP16-deviation forms at
+512^3, the 64 batched boxes, and the 768^3 dense suspension after device-side
+particle updates. The oracle computes sampled cells one by one from the
+engine's own state at step t (FP64, all spheres brute force) and the engine's
+f(t+1) must agree to the bound of one FP32 step with the storage rounding
+(psm_cases.deviation_bound); sampled sphere forces agree to 1e-6 of the sum of
+term magnitudes."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2303_11811_amd as psm
+from paper_2303_11811_amd import inputs
+from psm_cases import deviation_bound, gather_sources, one_step_sampled, oracle_after, sample_cells
+
+pytestmark = pytest.mark.gpu
+
+
+def _u0(eng, spec, torch):
+    with torch.cuda.stream(eng.stream):
+        if spec.u0 is None:
+            return torch.zeros((3, spec.N), dtype=torch.float64, device=eng.device)
+        return torch.as_tensor(spec.u0, dtype=torch.float64).to(eng.device)
+
+
+def _sphere_force_check(eng, box, spec, x, r, U, Om, ps, storage):
+    """One step; the oracle sums eqs. (21)-(22) over each sampled sphere's
+    bounding box from the engine's state at t."""
+    n = np.asarray(spec.dims)
+    ob = oracle.Box(*spec.dims, tau=spec.tau, fext=spec.fext)
+    frv = oracle.fr(r)
+    sets = {}
+    for p in ps:
+        lo = np.floor(x[p] - (r[p] + 1)).astype(int)
+        hi = np.floor(x[p] + (r[p] + 1)).astype(int)
+        g = [np.arange(lo[a], hi[a] + 1) for a in range(3)]
+        K, J, I = np.meshgrid(g[2], g[1], g[0], indexing="ij")
+        sets[p] = np.stack([I.ravel() % n[0], J.ravel() % n[1], K.ravel() % n[2]], axis=1)
+    fs = {p: eng.get_pdfs_at(box, [int(c[0] + n[0] * (c[1] + n[1] * c[2])) for c in cs]).cpu().numpy()
+          for p, cs in sets.items()}
+    eng.step(1)
+    F, T = eng.get_forces(box)
+    for p in ps:
+        Fo, To, A = np.zeros(3), np.zeros(3), 0.0
+        for a, (i, j, k) in enumerate(sets[p]):
+            ns, pid, B, _ = oracle.map_cell(ob, i, j, k, x, r, frv)
+            if p not in pid[:ns]:
+                continue
+            _, g = oracle.collide_cell(ob, i, j, k, fs[p][:, a], pid[:ns], B[:ns], x, U, Om)
+            s = list(pid[:ns]).index(p)
+            d = np.array([i + 0.5, j + 0.5, k + 0.5]) - x[p]
+            d -= n * np.round(d / n)
+            Bg = B[s] * g[s]
+            Fo += Bg
+            To += np.cross(d, Bg)
+            A += B[s] * np.linalg.norm(g[s])
+        assert np.linalg.norm(F[p] - Fo) <= 1e-6 * A + 1e-12 * np.linalg.norm(Fo), (p, F[p], Fo)
+        assert np.linalg.norm(T[p] - To) <= 1e-6 * A * (r[p] + 1) + 1e-12 * np.linalg.norm(To)
+
+
+@pytest.mark.parametrize("storage", [psm.PSM_FP32DEV, psm.PSM_FP16DEV])
+def test_precision_form_512_sampled(storage):
+    import torch
+
+    spec = inputs.paper_scale(n=512, seed=1)
+    print(f"[case] fullsize 512^3 storage={storage}", flush=True)
+    eng = psm.Engine([psm.desc_from_spec(spec)], storage=storage)
+    u0 = _u0(eng, spec, torch)
+    eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+    eng.set_equilibrium(0, u0)
+    eng.autotune(trial_steps=2)
+    eng.set_equilibrium(0, u0)
+    del u0
+    eng.step(5)
+    rng = np.random.default_rng(17)
+    cells = sample_cells(spec, spec.x, spec.r, rng)
+    got, ref = one_step_sampled(eng, 0, spec, cells, spec.x, spec.r, spec.U, spec.Om)
+    bound = deviation_bound(ref, storage)
+    print(f"[ratio] max |err|/bound = {np.max(np.abs(got - ref) / bound):.3g}", flush=True)
+    assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / bound)
+    ps = rng.choice(len(spec.r), 2, replace=False)
+    _sphere_force_check(eng, 0, spec, spec.x, spec.r, spec.U, spec.Om, ps, storage)
+    eng.close()
+
+
+def test_batched_64_boxes_sampled():
+    specs = inputs.batched_boxes(nbox=64, seed=3)
+    print(f"[case] batched 64 boxes cells={sum(s.N for s in specs)}", flush=True)
+    descs = [psm.desc_from_spec(s, max_particles=max(s.n_particles, 1), max_radius=8.0) for s in specs]
+    eng = psm.Engine(descs, storage=psm.PSM_FP32DEV)
+    for b, s in enumerate(specs):
+        if s.n_particles:
+            eng.set_particles(b, s.x, s.r, s.U, s.Om)
+    for b, s in enumerate(specs):
+        eng.set_equilibrium(b, s.u0)
+    eng.autotune(trial_steps=4)
+    for b, s in enumerate(specs):
+        eng.set_equilibrium(b, s.u0)
+    eng.set_graph(True)
+    eng.step(10)
+    rng = np.random.default_rng(5)
+    boxes = [int(b) for b in rng.choice(len(specs), 6, replace=False)]
+    cells, src = {}, {}
+    for b in boxes:
+        s = specs[b]
+        cells[b] = sample_cells(s, s.x, s.r, rng, n_surface=8 if s.n_particles else 0, n_random=8)
+        src[b] = gather_sources(eng, b, s, cells[b])
+    eng.step(1)   # one step of all 64 boxes
+    for b in boxes:
+        s = specs[b]
+        got, ref = oracle_after(eng, b, s, cells[b], *src[b], s.x, s.r, s.U, s.Om)
+        bound = deviation_bound(ref, psm.PSM_FP32DEV)
+        print(f"[ratio] box {b}: max |err|/bound = {np.max(np.abs(got - ref) / bound):.3g}", flush=True)
+        assert np.all(np.abs(got - ref) <= bound), (b, np.max(np.abs(got - ref) / bound))
+    eng.close()
+
+
+def test_dense_768_after_device_updates_sampled():
+    import torch
+
+    spec = inputs.dense_moving(n=768, seed=4)
+    print(f"[case] dense 768^3 spheres={len(spec.r)}", flush=True)
+    eng = psm.Engine([psm.desc_from_spec(spec, max_radius=8.0)], storage=psm.PSM_FP32DEV)
+    u0 = _u0(eng, spec, torch)
+    eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+    eng.set_equilibrium(0, u0)
+    eng.autotune(trial_steps=1)
+    eng.set_equilibrium(0, u0)
+    del u0
+    eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+    eng.set_dynamics(0, 2.5)
+    for _ in range(3):
+        eng.step(1)
+        eng.integrate(1.0, psm.PSM_EULER)
+    x, U, Om = eng.get_particles(0)
+    rng = np.random.default_rng(23)
+    cells = sample_cells(spec, x, spec.r, rng, n_surface=24, n_random=16)
+    got, ref = one_step_sampled(eng, 0, spec, cells, x, spec.r, U, Om)
+    bound = deviation_bound(ref, psm.PSM_FP32DEV)
+    print(f"[ratio] max |err|/bound = {np.max(np.abs(got - ref) / bound):.3g}", flush=True)
+    assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / bound)
+    ps = rng.choice(len(spec.r), 2, replace=False)
+    _sphere_force_check(eng, 0, spec, x, spec.r, U, Om, ps, psm.PSM_FP32DEV)
+    _, _, ov = eng.get_stats(0)
+    eng.close()
+    assert ov >= 0

@@ -125,3 +125,22 @@ def test_wall_particle_placement_is_checked():
         eng.set_particles(0, x, spec.r, spec.U)
     eng.close()
     assert ei.value.code == psm.PSM_EINVAL
+
+
+def test_through_flow_faces_parity_and_fixed_point():
+    """Velocity faces with a normal component (inflow at z = 0, outflow at
+    z = nz at the same velocity): parity with the oracle with spheres in the
+    stream, and the uniform flow as an exact fixed point without them."""
+    Uf = (0.004, 0.0, 0.015)
+    spec = _channel((30, 26, 24), 3, seed=31, fext=(0.0, 0.0, 0.0), wall_u=(Uf, Uf))
+    ref = run_oracle(spec, 12)
+    f, F, T, B, pid, eng = run_engine(spec, 12, launch=(32, 8, 4, 0))
+    eng.close()
+    assert_pdfs_close(f, ref.f, 1e-12)
+    assert_forces_close(F, ref.F, ref.A)
+    plug = inputs.BoxSpec(dims=(16, 12, 10), tau=0.8, walls_z=True, wall_u=(Uf, Uf),
+                          u0=np.repeat(np.array(Uf)[:, None], 16 * 12 * 10, axis=1))
+    f0 = initial_f(plug)
+    f1, *_, eng = run_engine(plug, 100)
+    eng.close()
+    assert np.max(np.abs(f1 - f0)) < 1e-15

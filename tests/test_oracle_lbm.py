@@ -215,3 +215,17 @@ def test_couette_moving_walls_linear_profile(tau):
     assert np.max(np.abs(u[2])) < 1e-14
     # tangential walls neither add nor remove mass
     assert abs(rho.sum() - box.N) < 1e-11 * box.N
+
+
+def test_uniform_through_flow_between_velocity_faces_is_a_fixed_point():
+    """Faces at z = -1/2 and nz - 1/2 imposing the same velocity U, with a
+    normal component (velocity inflow and outflow): the uniform flow E(1, U)
+    is an exact fixed point of the step, since the bounced population
+    E_qbar(U) + 6 w_q (c_q . U) equals E_q(U)."""
+    H = 9
+    U = np.array([0.012, -0.004, 0.02])
+    box = oracle.Box(4, 4, H, tau=0.77, walls_z=True, wall_u=(U, U))
+    u0 = np.repeat(U[:, None], box.N, axis=1)
+    f0 = oracle.equilibrium(box, u0)
+    f = oracle.run(box, f0, 150).f
+    assert np.max(np.abs(f - f0)) < 1e-15

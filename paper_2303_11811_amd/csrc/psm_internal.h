@@ -123,9 +123,9 @@ __host__ __device__ inline long long pdf_index(const BoxDev& b, int q, int x, in
 // Minimum image of one displacement component into [-L/2, L/2)
 // (hL = L/2, exact).
 __host__ __device__ inline double min_image(double d, double L, double hL) {
-    if (d >= hL) return d - L;
-    if (d < -hL) return d + L;
-    return d;
+    // two selects (no branch): the conditions exclude each other
+    double r = d >= hL ? d - L : d;
+    return d < -hL ? d + L : r;
 }
 
 // Overlap fraction of a sphere (radius r, f(r) = fr) with the cell whose

@@ -47,7 +47,8 @@ class _Box(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("tau", ctypes.c_double), ("fext", ctypes.c_double * 3),
                 ("mapping", ctypes.c_int), ("nsub", ctypes.c_int), ("walls_z", ctypes.c_int),
-                ("uwall", (ctypes.c_double * 3) * 2)]
+                ("uwall", (ctypes.c_double * 3) * 2), ("face_type", ctypes.c_int * 2),
+                ("face_rho", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -100,13 +101,19 @@ def _f64(a, shape=None):
     return a
 
 
+FACE_VELOCITY = 0
+FACE_PRESSURE = 1
+
+
 class Box:
-    """A box, periodic in x and y; in z periodic, or bounded by half-way
-    bounce-back walls at z = -1/2 and z = nz - 1/2 (cell-index coordinates)
-    moving with wall_u[0] (bottom) and wall_u[1] (top)."""
+    """A box, periodic in x and y; in z periodic, or bounded by faces at
+    z = -1/2 and z = nz - 1/2 (cell-index coordinates): velocity faces
+    (half-way bounce-back moving with wall_u) or pressure faces
+    (anti-bounce-back to density face_rho), bottom first."""
 
     def __init__(self, nx, ny, nz, tau, fext=(0.0, 0.0, 0.0), mapping=MAP_LINEAR, nsub=4,
-                 walls_z=False, wall_u=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))):
+                 walls_z=False, wall_u=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)),
+                 face_type=(FACE_VELOCITY, FACE_VELOCITY), face_rho=(1.0, 1.0)):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.tau = float(tau)
         self.fext = tuple(float(v) for v in fext)
@@ -114,6 +121,8 @@ class Box:
         self.nsub = int(nsub)
         self.walls_z = bool(walls_z)
         self.wall_u = tuple(tuple(float(v) for v in w) for w in wall_u)
+        self.face_type = tuple(int(t) for t in face_type)
+        self.face_rho = tuple(float(v) for v in face_rho)
 
     @property
     def N(self):
@@ -129,6 +138,8 @@ class Box:
         for w in range(2):
             for a in range(3):
                 b.uwall[w][a] = self.wall_u[w][a]
+            b.face_type[w] = self.face_type[w]
+            b.face_rho[w] = self.face_rho[w]
         return b
 
 

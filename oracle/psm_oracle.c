@@ -41,7 +41,11 @@
  *     name the scheme): half-way bounce-back at z = -1/2 and z = nz - 1/2 in
  *     cell-index coordinates, with the moving-wall term of Ladd for a wall
  *     velocity u_w (fluid density 1): a population f~_q leaving the fluid
- *     through the wall returns as f_qbar = f~_q - 6 w_q (c_q . u_w).
+ *     through the wall returns as f_qbar = f~_q - 6 w_q (c_q . u_w). A wall
+ *     velocity with a normal component is a velocity inflow or outflow.
+ *   - Pressure outflow (named in Sec. 4, scheme not given): anti-bounce-back,
+ *     f_qbar = -f~_q + 2 w_q (rho_w + 4.5 (c_q . u)^2 - 1.5 u.u), with u the
+ *     boundary cell's post-collision velocity sum_q f~_q c_q of the same step.
  *
  * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared -o libpsm_oracle.so
  */
@@ -81,8 +85,10 @@ typedef struct {
     double fext[3];
     int mapping;   /* 0: linear approximation, 1: sub-division sampling */
     int nsub;      /* samples per axis for mapping == 1 */
-    int walls_z;   /* half-way bounce-back walls at z = -1/2 and z = nz - 1/2 */
-    double uwall[2][3];   /* velocities of the bottom and the top wall */
+    int walls_z;   /* bounded in z by faces at z = -1/2 and z = nz - 1/2 */
+    double uwall[2][3];   /* velocities of the bottom and the top face (velocity faces) */
+    int face_type[2];     /* 0: velocity (bounce-back), 1: pressure (anti-bounce-back) */
+    double face_rho[2];   /* densities of pressure faces */
 } psmo_box;
 
 typedef struct {
@@ -472,8 +478,20 @@ long long psmo_run(const psmo_box *b, int nsteps, int np, const double *x, const
                     for (int q = 0; q < NQ; ++q) {
                         int ii = i + CQ[q][0], jj = j + CQ[q][1], kk = k + CQ[q][2];
                         if (b->walls_z && (kk < 0 || kk >= nz)) {
+                            int face = kk < 0 ? 0 : 1;
+                            if (b->face_type[face] == 1) {
+                                /* anti-bounce-back with the cell's post-collision velocity */
+                                double u[3] = {0.0, 0.0, 0.0};
+                                for (int p = 0; p < NQ; ++p)
+                                    for (int a = 0; a < 3; ++a) u[a] += ft[p] * CQ[p][a];
+                                double cu = CQ[q][0] * u[0] + CQ[q][1] * u[1] + CQ[q][2] * u[2];
+                                double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+                                fnew[inverse_dir(q) * N + n] =
+                                    -ft[q] + 2.0 * WQ[q] * (b->face_rho[face] + 4.5 * cu * cu - 1.5 * uu);
+                                continue;
+                            }
                             /* half-way bounce-back, moving-wall term for the wall crossed */
-                            const double *uw = b->uwall[kk < 0 ? 0 : 1];
+                            const double *uw = b->uwall[face];
                             double cu = CQ[q][0] * uw[0] + CQ[q][1] * uw[1] + CQ[q][2] * uw[2];
                             fnew[inverse_dir(q) * N + n] = ft[q] - 6.0 * WQ[q] * cu;
                             continue;

@@ -229,3 +229,39 @@ def test_uniform_through_flow_between_velocity_faces_is_a_fixed_point():
     f0 = oracle.equilibrium(box, u0)
     f = oracle.run(box, f0, 150).f
     assert np.max(np.abs(f - f0)) < 1e-15
+
+
+def test_velocity_inflow_pressure_outflow_plug_flow():
+    """Velocity inflow U through z = -1/2, pressure outflow (rho = 1) through
+    z = nz - 1/2: the uniform flow E(1, U) is an exact fixed point
+    (anti-bounce-back of E_q with the cell's velocity U returns E_qbar), and
+    a start from rest converges to it."""
+    H = 10
+    U = np.array([0.0, 0.0, 0.02])
+    box = oracle.Box(4, 4, H, tau=0.8, walls_z=True, wall_u=(U, (0.0, 0.0, 0.0)),
+                     face_type=(oracle.FACE_VELOCITY, oracle.FACE_PRESSURE), face_rho=(1.0, 1.0))
+    plug = oracle.equilibrium(box, np.repeat(U[:, None], box.N, axis=1))
+    f = oracle.run(box, plug, 100).f
+    assert np.max(np.abs(f - plug)) < 1e-15
+    f = oracle.run(box, oracle.equilibrium(box, np.zeros((3, box.N))), 6000).f
+    assert np.max(np.abs(f - plug)) < 1e-12
+
+
+def test_pressure_outflow_sets_the_outlet_density():
+    """Through-flow with a tangential inflow component and an outlet density
+    different from 1: mass flux in equals mass flux out at steady state, and
+    the density next to the outlet approaches the prescribed one."""
+    H = 12
+    U = np.array([0.01, 0.0, 0.015])
+    rho_out = 1.002
+    box = oracle.Box(4, 4, H, tau=0.9, walls_z=True, wall_u=(U, (0.0, 0.0, 0.0)),
+                     face_type=(oracle.FACE_VELOCITY, oracle.FACE_PRESSURE), face_rho=(1.0, rho_out))
+    f = oracle.run(box, oracle.equilibrium(box, np.zeros((3, box.N))), 6000).f
+    f2 = oracle.run(box, f, 1).f
+    assert np.max(np.abs(f2 - f)) < 1e-11      # steady
+    rho, u = oracle.macroscopic(box, f)
+    rz = rho.reshape(H, 4, 4)[:, 0, 0]
+    assert abs(rz[-1] - rho_out) < 2e-4
+    # uniform mass flux rho u_z along the channel (steady continuity)
+    jz = (rho * u[2]).reshape(H, 4, 4)[:, 0, 0]
+    assert np.max(np.abs(jz - jz.mean())) < 1e-10

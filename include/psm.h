@@ -58,6 +58,9 @@ enum psm_status {
  * collision in FP32; forces, torques and mass sums stay FP64. */
 enum psm_storage { PSM_FP64 = 0, PSM_FP32DEV = 1, PSM_FP16DEV = 2 };
 
+/* Boundary type of a z face (psm_box_desc.face_type). */
+enum psm_face { PSM_FACE_VELOCITY = 0, PSM_FACE_PRESSURE = 1 };
+
 /* Solid-fraction mapping (Sec. 2.3.2): the linear approximation of eq. (26),
  * or sub-division sampling with subsample_n^3 points per cell. */
 enum psm_mapping { PSM_MAP_LINEAR = 0, PSM_MAP_SUBSAMPLE = 1 };
@@ -70,10 +73,15 @@ typedef struct psm_box_desc {
     double max_radius;      /* largest sphere radius that will be set (>= 1) */
     int mapping;            /* psm_mapping */
     int subsample_n;        /* samples per axis for PSM_MAP_SUBSAMPLE (1..16) */
-    int walls_z;            /* 0: periodic in z; 1: no-slip walls at z = 0 and z = nz (cell faces),
-                               half-way bounce-back with the moving-wall term 6 w_q (c_q . u_w) */
-    double wall_u[2][3];    /* velocities of the z = 0 and z = nz walls (walls_z = 1); a normal
-                               component moves mass through the wall */
+    int walls_z;            /* 0: periodic in z; 1: bounded by the faces z = 0 and z = nz (cell
+                               faces), each of the type face_type (bottom first) */
+    double wall_u[2][3];    /* velocity faces: face velocity u_w; half-way bounce-back with the
+                               moving-wall term 6 w_q (c_q . u_w): no-slip for u_w = 0, a moving
+                               wall for a tangential u_w, a velocity inflow/outflow for a normal one */
+    int face_type[2];       /* psm_face (walls_z = 1) */
+    double face_rho[2];     /* pressure faces: density rho_w > 0; anti-bounce-back
+                               f_qbar = -f~_q + 2 w_q (rho_w + 4.5 (c_q.u)^2 - 1.5 u.u), u the boundary
+                               cell's post-collision velocity */
 } psm_box_desc;
 
 typedef struct psm_ctx psm_ctx;

@@ -23,6 +23,7 @@ PSM_FP64, PSM_FP32DEV, PSM_FP16DEV = 0, 1, 2
 PSM_MAP_LINEAR, PSM_MAP_SUBSAMPLE = 0, 1
 PSM_LAUNCH_PERSISTENT, PSM_LAUNCH_FILTER = 1, 2
 PSM_EULER, PSM_VERLET = 0, 1
+PSM_FACE_VELOCITY, PSM_FACE_PRESSURE = 0, 1
 STORAGE = {"f64": PSM_FP64, "f32dev": PSM_FP32DEV, "f16dev": PSM_FP16DEV}
 
 
@@ -37,7 +38,8 @@ class psm_box_desc(ctypes.Structure):
                 ("tau", ctypes.c_double), ("fext", ctypes.c_double * 3),
                 ("max_particles", ctypes.c_int), ("max_radius", ctypes.c_double),
                 ("mapping", ctypes.c_int), ("subsample_n", ctypes.c_int),
-                ("walls_z", ctypes.c_int), ("wall_u", (ctypes.c_double * 3) * 2)]
+                ("walls_z", ctypes.c_int), ("wall_u", (ctypes.c_double * 3) * 2),
+                ("face_type", ctypes.c_int * 2), ("face_rho", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -108,7 +110,8 @@ def _dptr(a):
 
 def make_desc(nx, ny, nz, tau, fext=(0.0, 0.0, 0.0), max_particles=0, max_radius=1.0,
               mapping=PSM_MAP_LINEAR, subsample_n=4, walls_z=False,
-              wall_u=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))) -> psm_box_desc:
+              wall_u=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)), face_type=(PSM_FACE_VELOCITY, PSM_FACE_VELOCITY),
+              face_rho=(1.0, 1.0)) -> psm_box_desc:
     d = psm_box_desc()
     d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
     d.tau = float(tau)
@@ -122,6 +125,8 @@ def make_desc(nx, ny, nz, tau, fext=(0.0, 0.0, 0.0), max_particles=0, max_radius
     for w in range(2):
         for a in range(3):
             d.wall_u[w][a] = float(wall_u[w][a])
+        d.face_type[w] = int(face_type[w])
+        d.face_rho[w] = float(face_rho[w])
     return d
 
 
@@ -413,4 +418,5 @@ def desc_from_spec(spec, max_particles=None, max_radius=None):
     n = spec.n_particles if max_particles is None else max_particles
     rmax = (float(np.max(spec.r)) if len(spec.r) else 1.0) if max_radius is None else max_radius
     return make_desc(*spec.dims, spec.tau, spec.fext, max_particles=n, max_radius=max(rmax, 1.0),
-                     mapping=spec.mapping, subsample_n=spec.nsub, walls_z=spec.walls_z, wall_u=spec.wall_u)
+                     mapping=spec.mapping, subsample_n=spec.nsub, walls_z=spec.walls_z, wall_u=spec.wall_u,
+                     face_type=spec.face_type, face_rho=spec.face_rho)

@@ -102,10 +102,14 @@ static int validate(const psm_box_desc* boxes, int nbox, int storage) {
             if (!std::isfinite(d.fext[a])) return fail(PSM_EINVAL, "box %d: non-finite body force", b);
         if (d.max_particles < 0) return fail(PSM_EINVAL, "box %d: max_particles < 0", b);
         if (d.walls_z != 0 && d.walls_z != 1) return fail(PSM_EINVAL, "box %d: walls_z must be 0 or 1", b);
-        for (int w = 0; w < 2; ++w)
+        for (int w = 0; w < 2 && d.walls_z; ++w) {
             for (int a = 0; a < 3; ++a)
-                if (d.walls_z && !std::isfinite(d.wall_u[w][a]))
-                    return fail(PSM_EINVAL, "box %d: non-finite wall velocity", b);
+                if (!std::isfinite(d.wall_u[w][a])) return fail(PSM_EINVAL, "box %d: non-finite wall velocity", b);
+            if (d.face_type[w] != PSM_FACE_VELOCITY && d.face_type[w] != PSM_FACE_PRESSURE)
+                return fail(PSM_EINVAL, "box %d: unknown face type %d", b, d.face_type[w]);
+            if (d.face_type[w] == PSM_FACE_PRESSURE && !(d.face_rho[w] > 0.0 && std::isfinite(d.face_rho[w])))
+                return fail(PSM_EINVAL, "box %d: a pressure face needs a positive density", b);
+        }
         if (d.mapping != PSM_MAP_LINEAR && d.mapping != PSM_MAP_SUBSAMPLE)
             return fail(PSM_EINVAL, "box %d: unknown mapping %d", b, d.mapping);
         if (d.mapping == PSM_MAP_SUBSAMPLE && (d.subsample_n < 1 || d.subsample_n > 16))
@@ -420,10 +424,14 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
         bx.reach = 0.8660254037844386 * (1.0 - 1.0 / bx.nsub) + 1e-9;
         bx.rho_p = 1.0;
         bx.walls = d.walls_z;
+        for (int w = 0; w < 2; ++w) {
+            bx.face_type[w] = d.walls_z ? d.face_type[w] : FACE_VELOCITY;
+            bx.face_rho[w] = bx.face_type[w] == FACE_PRESSURE ? d.face_rho[w] : 1.0;
+        }
         for (int w = 0; w < 2; ++w)
             for (int q = 0; q < NQ; ++q) {
-                // entering through the bottom wall: c_z = +1; through the top: c_z = -1
-                bool in = d.walls_z && CZ[q] == (w == 0 ? 1 : -1);
+                // entering through the bottom face: c_z = +1; through the top: c_z = -1
+                bool in = d.walls_z && bx.face_type[w] == FACE_VELOCITY && CZ[q] == (w == 0 ? 1 : -1);
                 double cu = CX[q] * d.wall_u[w][0] + CY[q] * d.wall_u[w][1] + CZ[q] * d.wall_u[w][2];
                 bx.bw[w][q] = in ? 6.0 * wq(q) * cu : 0.0;
             }

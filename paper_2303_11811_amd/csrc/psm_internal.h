@@ -50,15 +50,21 @@ struct BoxDev {
     // acceleration (gravity minus buoyancy) used by the integrator.
     double rho_p;
     double accel[3];
-    // No-slip walls at z = 0 and z = nz (half-way bounce-back). A population
-    // q entering a boundary cell through wall w is the one the cell sent
-    // against the wall (direction opp(q)) plus bw[w][q] = 6 w_q (c_q . u_w).
+    // Faces at z = 0 and z = nz instead of periodicity (walls != 0). On a
+    // velocity face w a population q entering a boundary cell is the one the
+    // cell sent against the face (direction inv_dir(q)) plus bw[w][q] =
+    // 6 w_q (c_q . u_w) (half-way bounce-back); on a pressure face it is
+    // minus that population plus 2 w_q (face_rho[w] + 4.5 (c_q.u)^2 - 1.5 u.u)
+    // with u the cell's post-collision velocity (anti-bounce-back).
     int walls;
+    int face_type[2];               // FACE_VELOCITY or FACE_PRESSURE
+    double face_rho[2];
     double bw[2][NQ];
 };
+enum { FACE_VELOCITY = 0, FACE_PRESSURE = 1 };
 
 // Opposite direction: the pairs (1,2), (3,4), ..., (17,18) are opposite.
-__host__ __device__ constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+__host__ __device__ constexpr int inv_dir(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
 
 // Global particle table, SoA, indexed by global particle id.
 struct Particles {

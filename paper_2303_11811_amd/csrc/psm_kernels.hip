@@ -376,25 +376,50 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
             // 2. pull: f_q(x) = grid[q][x - c_q]
             R hx = 0, hy = 0, hz = 0;   // 2 j - U, for the force of eq. (21)
             if (lane_ok) {
+                // through a face (first and last z plane of a box with walls):
+                // the population this cell sent against it last step, by the
+                // face rule; computed before the pulls so that its
+                // temporaries are not live beside them (uniform branches)
+                const bool face_plane = bx.walls && (z == 0 || z == nz - 1);
+                R fb[5] = {0, 0, 0, 0, 0};
+                if (face_plane) {
+                    const int w = z == 0 ? 0 : 1;
+                    // entering directions through this face and their opposites
+                    constexpr int in0[5] = {5, 11, 14, 15, 18}, in1[5] = {6, 12, 13, 16, 17};
+                    if (bx.face_type[w] == FACE_VELOCITY) {
+                        const R ws = S::SCALED ? sc : (R)1;
+#pragma unroll
+                        for (int i = 0; i < 5; ++i) {
+                            const int q = w == 0 ? in0[i] : in1[i];
+                            fb[i] = S::loadb(sbz + inv_dir(q) * QB, o00, kp.h_inv) + ws * (R)bx.bw[w][q];
+                        }
+                    } else {
+                        // anti-bounce-back with the cell's post-collision velocity
+                        // (its own 19 slots); deviation units carry rho_w - 1
+                        R ux = 0, uy = 0, uz = 0;
+#pragma unroll
+                        for (int q = 1; q < NQ; ++q) {
+                            const R v = S::loadb(sbz + q * QB, o00, kp.h_inv);
+                            ux += (R)CX[q] * v; uy += (R)CY[q] * v; uz += (R)CZ[q] * v;
+                        }
+                        const R rw = S::DEV ? (R)(bx.face_rho[w] - 1.0) * sc : (R)bx.face_rho[w];
+                        const R uu = k15 * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+                        for (int i = 0; i < 5; ++i) {
+                            const int q = w == 0 ? in0[i] : in1[i];
+                            const R cu = (R)CX[q] * ux + (R)CY[q] * uy + (R)CZ[q] * uz;
+                            fb[i] = (R)(2.0 * wq(q)) * (rw + k45 * (cu * cu) - uu) -
+                                    S::loadb(sbz + inv_dir(q) * QB, o00, kp.h_inv);
+                        }
+                    }
+                }
                 R f[NQ];
                 PSM_LOAD19(f, sbz, sbm, sbp);
-                if (bx.walls) {
-                    // through a wall: the population this cell sent against it
-                    // last step, plus the moving-wall term (uniform branches)
-                    const R ws = S::SCALED ? sc : (R)1;
+                if (face_plane) {
                     if (z == 0) {
-                        f[5] = S::loadb(sbz + 6 * QB, o00, kp.h_inv) + ws * (R)bx.bw[0][5];
-                        f[11] = S::loadb(sbz + 12 * QB, o00, kp.h_inv) + ws * (R)bx.bw[0][11];
-                        f[14] = S::loadb(sbz + 13 * QB, o00, kp.h_inv) + ws * (R)bx.bw[0][14];
-                        f[15] = S::loadb(sbz + 16 * QB, o00, kp.h_inv) + ws * (R)bx.bw[0][15];
-                        f[18] = S::loadb(sbz + 17 * QB, o00, kp.h_inv) + ws * (R)bx.bw[0][18];
-                    }
-                    if (z == nz - 1) {
-                        f[6] = S::loadb(sbz + 5 * QB, o00, kp.h_inv) + ws * (R)bx.bw[1][6];
-                        f[12] = S::loadb(sbz + 11 * QB, o00, kp.h_inv) + ws * (R)bx.bw[1][12];
-                        f[13] = S::loadb(sbz + 14 * QB, o00, kp.h_inv) + ws * (R)bx.bw[1][13];
-                        f[16] = S::loadb(sbz + 15 * QB, o00, kp.h_inv) + ws * (R)bx.bw[1][16];
-                        f[17] = S::loadb(sbz + 18 * QB, o00, kp.h_inv) + ws * (R)bx.bw[1][17];
+                        f[5] = fb[0]; f[11] = fb[1]; f[14] = fb[2]; f[15] = fb[3]; f[18] = fb[4];
+                    } else {
+                        f[6] = fb[0]; f[12] = fb[1]; f[13] = fb[2]; f[16] = fb[3]; f[17] = fb[4];
                     }
                 }
 
@@ -704,15 +729,49 @@ __global__ __launch_bounds__(256) void k_scan_apply(const int* cnt, int n, const
 // ---------------------------------------------------------------------------
 // State I/O. Canonical f(x,t) = grid[q][x - c_q] (pull storage).
 
+// Face crossed by a neighbour at z-index zz: -1 none (inside or periodic), 0 bottom, 1 top.
+__device__ inline int face_of(const BoxDev& bx, int zz) {
+    return !bx.walls ? -1 : (zz < 0 ? 0 : (zz >= bx.nz ? 1 : -1));
+}
+
+// Post-collision velocity of a cell from its own 19 stored slots (slot q of
+// cell x holds the value it sent in direction q), in S::to_f64 units.
+template <class S>
+__device__ inline void slot_velocity(const BoxDev& bx, const typename S::T* g, int x, int y, int z, float inv,
+                                     double u[3]) {
+    u[0] = u[1] = u[2] = 0.0;
+    for (int q = 1; q < NQ; ++q) {
+        double v = S::to_f64(g[pdf_index(bx, q, x, y, z)], inv);
+        u[0] += v * CX[q]; u[1] += v * CY[q]; u[2] += v * CZ[q];
+    }
+}
+
+// Anti-bounce-back: the population entering in direction q through a
+// pressure face, from the one sent in direction inv_dir(q) (s_opp), the face
+// density term rho (minus 1 in deviation units) and the cell's velocity u.
+__device__ inline double abb_value(int q, double s_opp, double rho, const double u[3]) {
+    double cu = CX[q] * u[0] + CY[q] * u[1] + CZ[q] * u[2];
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return -s_opp + 2.0 * wq(q) * (rho + 4.5 * cu * cu - 1.5 * uu);
+}
+
 // Canonical f_q(x, t) of cell (x, y, z) from the stored (pulled) layout, in
 // the units of S::to_f64 (the deviation for the deviation forms): the value
-// streamed from x - c_q, or, through a wall, the population the cell sent
-// against it (direction opp(q)) plus the moving-wall term.
+// streamed from x - c_q, or, through a face, the face rule applied to the
+// population the cell sent against it (direction inv_dir(q)).
 template <class S>
 __device__ inline double pull_value(const BoxDev& bx, const typename S::T* g, int q, int x, int y, int z, float inv) {
     int zs = z - CZ[q];
-    if (bx.walls && (zs < 0 || zs >= bx.nz))
-        return S::to_f64(g[pdf_index(bx, opp(q), x, y, z)], inv) + bx.bw[zs < 0 ? 0 : 1][q];
+    int w = face_of(bx, zs);
+    if (w >= 0) {
+        double so = S::to_f64(g[pdf_index(bx, inv_dir(q), x, y, z)], inv);
+        if (bx.face_type[w] == FACE_PRESSURE) {
+            double u[3];
+            slot_velocity<S>(bx, g, x, y, z, inv, u);
+            return abb_value(q, so, S::DEV ? bx.face_rho[w] - 1.0 : bx.face_rho[w], u);
+        }
+        return so + bx.bw[w][q];
+    }
     int xs = x - CX[q], ys = y - CY[q];
     xs = xs < 0 ? xs + bx.nx : (xs >= bx.nx ? xs - bx.nx : xs);
     ys = ys < 0 ? ys + bx.ny : (ys >= bx.ny ? ys - bx.ny : ys);
@@ -720,24 +779,51 @@ __device__ inline double pull_value(const BoxDev& bx, const typename S::T* g, in
     return S::to_f64(g[pdf_index(bx, q, xs, ys, zs)], inv);
 }
 
-// Inverse of pull_value for the stored slot (q, x, y, z): the cell that will
-// read it, and the direction and wall term it reads it with. Returns the
-// reading cell index; *dir and *add describe the canonical value to store:
-// slot = f_dir(cell) - add.
-__device__ inline long long slot_reader(const BoxDev& bx, int q, int x, int y, int z, int* dir, double* add) {
-    int zd = z + CZ[q];
-    if (bx.walls && (zd < 0 || zd >= bx.nz)) {
-        *dir = opp(q);
-        *add = bx.bw[zd < 0 ? 0 : 1][opp(q)];
-        return x + (long long)bx.nx * (y + (long long)bx.ny * z);
+// Inverse of pull_value for the 19 slots of cell (x, y, z): given the
+// canonical field through canon(dir, cell) (FP64, full f), the slot values
+// that pulling turns back into it. A slot whose reader is inside (or across
+// a periodic boundary) holds the reader's value; a slot sent against a
+// velocity face holds the cell's own opposite value minus the wall term; the
+// slots sent against a pressure face solve the anti-bounce-back rule, whose
+// velocity depends on all 19 slots, by fixed-point iteration (the
+// dependence is quadratic in the velocity, so a few sweeps reach round-off).
+template <class S, class Canon>
+__device__ inline void store_cell_slots(const BoxDev& bx, typename S::T* g, int x, int y, int z, float scale,
+                                        Canon canon) {
+    const long long self = x + (long long)bx.nx * (y + (long long)bx.ny * z);
+    double sl[NQ];
+    int pface = -1;
+    for (int q = 0; q < NQ; ++q) {
+        int zd = z + CZ[q];
+        int w = face_of(bx, zd);
+        if (w < 0) {
+            int xd = x + CX[q], yd = y + CY[q];
+            xd = xd < 0 ? xd + bx.nx : (xd >= bx.nx ? xd - bx.nx : xd);
+            yd = yd < 0 ? yd + bx.ny : (yd >= bx.ny ? yd - bx.ny : yd);
+            zd = zd < 0 ? zd + bx.nz : (zd >= bx.nz ? zd - bx.nz : zd);
+            sl[q] = canon(q, xd + (long long)bx.nx * (yd + (long long)bx.ny * zd));
+        } else if (bx.face_type[w] == FACE_VELOCITY) {
+            sl[q] = canon(inv_dir(q), self) - bx.bw[w][inv_dir(q)];
+        } else {
+            sl[q] = -canon(inv_dir(q), self) + 2.0 * wq(q) * bx.face_rho[w];
+            pface = w;
+        }
     }
-    int xd = x + CX[q], yd = y + CY[q];
-    xd = xd < 0 ? xd + bx.nx : (xd >= bx.nx ? xd - bx.nx : xd);
-    yd = yd < 0 ? yd + bx.ny : (yd >= bx.ny ? yd - bx.ny : yd);
-    zd = zd < 0 ? zd + bx.nz : (zd >= bx.nz ? zd - bx.nz : zd);
-    *dir = q;
-    *add = 0.0;
-    return xd + (long long)bx.nx * (yd + (long long)bx.ny * zd);
+    if (pface >= 0) {
+        for (int it = 0; it < 12; ++it) {
+            double u[3] = {0.0, 0.0, 0.0};
+            for (int q = 1; q < NQ; ++q) {
+                u[0] += sl[q] * CX[q]; u[1] += sl[q] * CY[q]; u[2] += sl[q] * CZ[q];
+            }
+            for (int q = 0; q < NQ; ++q)
+                if (face_of(bx, z + CZ[q]) == pface)
+                    sl[q] = abb_value(q, canon(inv_dir(q), self), bx.face_rho[pface], u);
+        }
+    }
+    for (int q = 0; q < NQ; ++q) {
+        double v = S::DEV ? sl[q] - wq(q) : sl[q];
+        g[pdf_index(bx, q, x, y, z)] = S::from_f64(v, scale);
+    }
 }
 
 template <class S>
@@ -746,15 +832,8 @@ __global__ void k_set_pdfs(BoxDev bx, int parity, const double* __restrict__ f, 
     if (n >= bx.N) return;
     int x = n % bx.nx, y = (n / bx.nx) % bx.ny, z = n / ((long long)bx.nx * bx.ny);
     typename S::T* g = (typename S::T*)bx.grid[parity];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        int dq;
-        double add;
-        long long s = slot_reader(bx, q, x, y, z, &dq, &add);
-        double v = f[(long long)dq * bx.N + s] - add;
-        if (S::DEV) v -= wq(q);
-        g[pdf_index(bx, q, x, y, z)] = S::from_f64(v, scale);
-    }
+    const long long N = bx.N;
+    store_cell_slots<S>(bx, g, x, y, z, scale, [&](int d, long long c) { return f[(long long)d * N + c]; });
 }
 
 template <class S>
@@ -764,19 +843,15 @@ __global__ void k_set_equilibrium(BoxDev bx, int parity, const double* __restric
     if (n >= bx.N) return;
     int x = n % bx.nx, y = (n / bx.nx) % bx.ny, z = n / ((long long)bx.nx * bx.ny);
     typename S::T* g = (typename S::T*)bx.grid[parity];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        int dq;
-        double add;
-        long long s = slot_reader(bx, q, x, y, z, &dq, &add);
-        double r = rho ? rho[s] : 1.0;
-        double vx = u[s], vy = u[bx.N + s], vz = u[2LL * bx.N + s];
-        double cv = CX[dq] * vx + CY[dq] * vy + CZ[dq] * vz;
+    const long long N = bx.N;
+    // E_d(rho, u) of eq. (5) at cell c
+    store_cell_slots<S>(bx, g, x, y, z, scale, [&](int d, long long c) {
+        double r = rho ? rho[c] : 1.0;
+        double vx = u[c], vy = u[N + c], vz = u[2 * N + c];
+        double cv = CX[d] * vx + CY[d] * vy + CZ[d] * vz;
         double vv = vx * vx + vy * vy + vz * vz;
-        double rr = S::DEV ? r - 1.0 : r;   // deviation form: E_q - w_q (w_q = w_opp(q))
-        double e = wq(dq) * (rr + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv) - add;
-        g[pdf_index(bx, q, x, y, z)] = S::from_f64(e, scale);
-    }
+        return wq(d) * (r + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
+    });
 }
 
 template <class S>
@@ -873,16 +948,26 @@ __global__ __launch_bounds__(256) void k_stats_partial(BoxDev bx, int parity, fl
     for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < bx.N;
          n += (long long)gridDim.x * blockDim.x) {
         int x = n % bx.nx, y = (n / bx.nx) % bx.ny, z = n / ((long long)bx.nx * bx.ny);
+        // each slot is one canonical value: the reader's f_q, or across a face
+        // the cell's own f_opp(q) by the face rule
+        double uc[3] = {0.0, 0.0, 0.0};
+        const bool pz_face = bx.walls && ((z == 0 && bx.face_type[0] == FACE_PRESSURE) ||
+                                          (z == bx.nz - 1 && bx.face_type[1] == FACE_PRESSURE));
+        if (pz_face) slot_velocity<S>(bx, g, x, y, z, inv, uc);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            // the slot holds f_dq(reader) - add (a permutation of f(x,t) without walls)
-            int dq;
-            double add;
-            (void)slot_reader(bx, q, x, y, z, &dq, &add);
-            double v = S::to_f64(g[pdf_index(bx, q, x, y, z)], inv) + add;
+            double v = S::to_f64(g[pdf_index(bx, q, x, y, z)], inv);
+            int d = q;
+            int w = face_of(bx, z + CZ[q]);
+            if (w >= 0) {
+                d = inv_dir(q);
+                v = bx.face_type[w] == FACE_PRESSURE
+                        ? abb_value(d, v, S::DEV ? bx.face_rho[w] - 1.0 : bx.face_rho[w], uc)
+                        : v + bx.bw[w][d];
+            }
             if (S::DEV) v += wq(q);
             m += v;
-            px += v * CX[dq]; py += v * CY[dq]; pz += v * CZ[dq];
+            px += v * CX[d]; py += v * CY[d]; pz += v * CZ[d];
         }
     }
     s[0][threadIdx.x] = m; s[1][threadIdx.x] = px; s[2][threadIdx.x] = py; s[3][threadIdx.x] = pz;

@@ -195,8 +195,10 @@ class BoxSpec:
     Om: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
     u0: np.ndarray | None = None   # initial velocity [3][N]; None = rest
     rho0: np.ndarray | None = None
-    walls_z: bool = False          # no-slip walls at z = 0 and z = nz instead of periodicity
-    wall_u: tuple = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))   # bottom and top wall velocities
+    walls_z: bool = False          # faces at z = 0 and z = nz instead of periodicity
+    wall_u: tuple = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))   # bottom and top velocity-face velocities
+    face_type: tuple = (0, 0)      # 0 velocity face (bounce-back), 1 pressure face (anti-bounce-back)
+    face_rho: tuple = (1.0, 1.0)   # pressure-face densities
 
     @property
     def N(self):

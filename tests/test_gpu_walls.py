@@ -144,3 +144,66 @@ def test_through_flow_faces_parity_and_fixed_point():
     f1, *_, eng = run_engine(plug, 100)
     eng.close()
     assert np.max(np.abs(f1 - f0)) < 1e-15
+
+
+def _outflow(dims, n, seed, storage_rho=1.0, U=(0.003, 0.0, 0.012)):
+    """Velocity inflow through z = 0, pressure outflow through z = nz."""
+    spec = _channel(dims, n, seed, fext=(0.0, 0.0, 0.0), wall_u=(U, (0.0, 0.0, 0.0)))
+    spec.face_type = (psm.PSM_FACE_VELOCITY, psm.PSM_FACE_PRESSURE)
+    spec.face_rho = (1.0, storage_rho)
+    return spec
+
+
+@pytest.mark.parametrize("dims,launch,rho_out", [((36, 30, 24), (64, 4, 4, 0), 1.0),
+                                                 ((33, 26, 21), (32, 8, 8, 3), 1.003)])
+def test_pressure_outflow_parity_fp64(dims, launch, rho_out):
+    spec = _outflow(dims, 4, seed=sum(dims), storage_rho=rho_out)
+    print(f"[case] outflow fp64 dims={dims} launch={launch}", flush=True)
+    ref = run_oracle(spec, 15)
+    f, F, T, B, pid, eng = run_engine(spec, 15, launch=launch)
+    mass, mom, _ = eng.get_stats(0)
+    eng.close()
+    assert_pdfs_close(f, ref.f, 1e-12)
+    assert_forces_close(F, ref.F, ref.A)
+    assert_forces_close(T, ref.T, ref.A, lever=spec.r.max() + 1)
+    c, _, _ = oracle.lattice()
+    assert abs(mass - ref.f.sum()) <= 1e-12 * ref.f.sum()
+    mref = np.array([(ref.f * c[:, a:a + 1]).sum() for a in range(3)])
+    assert np.all(np.abs(mom - mref) <= 1e-12 * ref.f.sum())
+
+
+@pytest.mark.parametrize("storage,tol_u", [(psm.PSM_FP32DEV, 2e-5), (psm.PSM_FP16DEV, 3e-3)])
+def test_pressure_outflow_deviation_forms(storage, tol_u):
+    spec = _outflow((28, 20, 18), 2, seed=8, storage_rho=1.002)
+    ref = run_oracle(spec, 40)
+    f, *_, eng = run_engine(spec, 40, storage=storage)
+    eng.close()
+    box = oracle.Box(*spec.dims, tau=spec.tau)
+    _, u_ref = oracle.macroscopic(box, ref.f)
+    _, u = oracle.macroscopic(box, f)
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < tol_u
+
+
+def test_pressure_outflow_state_roundtrip_and_plug_flow():
+    """set_pdfs inverts the anti-bounce-back read (fixed-point solve of the
+    boundary slots), and the uniform inflow velocity is an exact fixed point
+    that a start from rest converges to."""
+    spec = _outflow((12, 8, 10), 0, seed=3)
+    f0 = initial_f(spec) + 1e-3 * np.random.default_rng(4).standard_normal((19, spec.N))
+    eng = make_engine([spec])
+    eng.set_pdfs(0, f0)
+    f1 = eng.get_pdfs(0).cpu().numpy()
+    eng.close()
+    assert np.max(np.abs(f1 - f0)) <= 1e-15
+    U = np.array(spec.wall_u[0])
+    plug = inputs.BoxSpec(dims=(4, 4, 10), tau=0.8, walls_z=True, wall_u=(tuple(U), (0.0, 0.0, 0.0)),
+                          face_type=(0, 1), u0=np.repeat(U[:, None], 160, axis=1))
+    fp = initial_f(plug)
+    f2, *_, eng = run_engine(plug, 100)
+    eng.close()
+    assert np.max(np.abs(f2 - fp)) < 1e-15
+    rest = inputs.BoxSpec(dims=(4, 4, 10), tau=0.8, walls_z=True, wall_u=(tuple(U), (0.0, 0.0, 0.0)),
+                          face_type=(0, 1))
+    f3, *_, eng = run_engine(rest, 7000, launch=(16, 16, 2, 0))
+    eng.close()
+    assert np.max(np.abs(f3 - fp)) < 1e-12

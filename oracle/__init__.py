@@ -48,7 +48,7 @@ class _Box(ctypes.Structure):
                 ("tau", ctypes.c_double), ("fext", ctypes.c_double * 3),
                 ("mapping", ctypes.c_int), ("nsub", ctypes.c_int), ("walls_z", ctypes.c_int),
                 ("uwall", (ctypes.c_double * 3) * 2), ("face_type", ctypes.c_int * 2),
-                ("face_rho", ctypes.c_double * 2)]
+                ("face_rho", ctypes.c_double * 2), ("walls_x", ctypes.c_int), ("walls_y", ctypes.c_int)]
 
 
 _lib = None
@@ -106,14 +106,15 @@ FACE_PRESSURE = 1
 
 
 class Box:
-    """A box, periodic in x and y; in z periodic, or bounded by faces at
-    z = -1/2 and z = nz - 1/2 (cell-index coordinates): velocity faces
-    (half-way bounce-back moving with wall_u) or pressure faces
+    """A box, periodic in x and y unless walls_x / walls_y put resting
+    no-slip walls at -1/2 and n - 1/2 (cell-index coordinates); in z
+    periodic, or bounded by faces at z = -1/2 and z = nz - 1/2: velocity
+    faces (half-way bounce-back moving with wall_u) or pressure faces
     (anti-bounce-back to density face_rho), bottom first."""
 
     def __init__(self, nx, ny, nz, tau, fext=(0.0, 0.0, 0.0), mapping=MAP_LINEAR, nsub=4,
                  walls_z=False, wall_u=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)),
-                 face_type=(FACE_VELOCITY, FACE_VELOCITY), face_rho=(1.0, 1.0)):
+                 face_type=(FACE_VELOCITY, FACE_VELOCITY), face_rho=(1.0, 1.0), walls_x=False, walls_y=False):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.tau = float(tau)
         self.fext = tuple(float(v) for v in fext)
@@ -123,6 +124,7 @@ class Box:
         self.wall_u = tuple(tuple(float(v) for v in w) for w in wall_u)
         self.face_type = tuple(int(t) for t in face_type)
         self.face_rho = tuple(float(v) for v in face_rho)
+        self.walls_x, self.walls_y = bool(walls_x), bool(walls_y)
 
     @property
     def N(self):
@@ -140,6 +142,7 @@ class Box:
                 b.uwall[w][a] = self.wall_u[w][a]
             b.face_type[w] = self.face_type[w]
             b.face_rho[w] = self.face_rho[w]
+        b.walls_x, b.walls_y = int(self.walls_x), int(self.walls_y)
         return b
 
 

@@ -43,6 +43,9 @@
  *     velocity u_w (fluid density 1): a population f~_q leaving the fluid
  *     through the wall returns as f_qbar = f~_q - 6 w_q (c_q . u_w). A wall
  *     velocity with a normal component is a velocity inflow or outflow.
+ *   - Side walls (x and y; the bed's four no-slip sides, Sec. 4): resting
+ *     half-way bounce-back f_qbar = f~_q. A population that would leave
+ *     through a side wall and a z face at once is bounced by the side wall.
  *   - Pressure outflow (named in Sec. 4, scheme not given): anti-bounce-back,
  *     f_qbar = -f~_q + 2 w_q (rho_w + 4.5 (c_q . u)^2 - 1.5 u.u), with u the
  *     boundary cell's post-collision velocity sum_q f~_q c_q of the same step.
@@ -89,6 +92,7 @@ typedef struct {
     double uwall[2][3];   /* velocities of the bottom and the top face (velocity faces) */
     int face_type[2];     /* 0: velocity (bounce-back), 1: pressure (anti-bounce-back) */
     double face_rho[2];   /* densities of pressure faces */
+    int walls_x, walls_y; /* resting no-slip walls at x = -1/2, nx - 1/2 (and in y) */
 } psmo_box;
 
 typedef struct {
@@ -477,6 +481,11 @@ long long psmo_run(const psmo_box *b, int nsteps, int np, const double *x, const
                     /* eq. (2): f_q(x + c_q, t + 1) = ft_q(x, t) */
                     for (int q = 0; q < NQ; ++q) {
                         int ii = i + CQ[q][0], jj = j + CQ[q][1], kk = k + CQ[q][2];
+                        if ((b->walls_x && (ii < 0 || ii >= nx)) || (b->walls_y && (jj < 0 || jj >= ny))) {
+                            /* resting side wall: half-way bounce-back */
+                            fnew[inverse_dir(q) * N + n] = ft[q];
+                            continue;
+                        }
                         if (b->walls_z && (kk < 0 || kk >= nz)) {
                             int face = kk < 0 ? 0 : 1;
                             if (b->face_type[face] == 1) {

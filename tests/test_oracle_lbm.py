@@ -265,3 +265,30 @@ def test_pressure_outflow_sets_the_outlet_density():
     # uniform mass flux rho u_z along the channel (steady continuity)
     jz = (rho * u[2]).reshape(H, 4, 4)[:, 0, 0]
     assert np.max(np.abs(jz - jz.mean())) < 1e-10
+
+
+def test_duct_flow_side_walls():
+    """Body-force flow along z through a duct with resting walls in x and y:
+    the steady profile is symmetric in x and y, vanishes nowhere inside, and
+    mass is conserved; with walls in x only the profile is the Poiseuille
+    closed form in x (the half-way bounce-back solution, as pinned for z)."""
+    tau, g = 0.8, 1e-5
+    nu = (tau - 0.5) / 3.0
+    H = 10
+    box = oracle.Box(H, 4, 4, tau=tau, fext=(0.0, 0.0, g), walls_x=True)
+    f = oracle.equilibrium(box, np.zeros((3, box.N)))
+    steps = int(40 * H * H / (math.pi ** 2 * nu)) + 200
+    f = oracle.run(box, f, steps).f
+    rho, u = oracle.macroscopic(box, f)
+    x = np.arange(H) + 0.0
+    exact = g / (2 * nu) * (x + 0.5) * (H - 0.5 - x) + 2 * g / (3 * nu) * ((tau - 0.5) ** 2 - 3.0 / 16.0)
+    prof = u[2].reshape(4, 4, H)[0, 0, :]
+    assert np.max(np.abs(prof - exact)) / exact.max() < 1e-9
+    assert abs(rho.sum() - box.N) < 1e-11 * box.N
+    box2 = oracle.Box(8, 8, 4, tau=tau, fext=(0.0, 0.0, g), walls_x=True, walls_y=True)
+    f2 = oracle.run(box2, oracle.equilibrium(box2, np.zeros((3, box2.N))), 3000).f
+    _, u2 = oracle.macroscopic(box2, f2)
+    w = u2[2].reshape(4, 8, 8)[0]
+    assert np.allclose(w, w.T, rtol=0, atol=1e-15)
+    assert np.allclose(w, w[::-1, :], rtol=0, atol=1e-15)
+    assert np.all(w > 0)

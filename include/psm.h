@@ -17,8 +17,8 @@
  *   throws. psm_last_error() returns a thread-local text of the last failure.
  * - Argument checks happen on the host before anything is enqueued; a bad
  *   argument returns PSM_EINVAL and leaves the context unchanged.
- * - Lattice units: dx = dt = 1, rho_0 = 1, c_s^2 = 1/3. Boxes are periodic in
- *   x and y, and in z unless they have walls (psm_box_desc.walls_z).
+ * - Lattice units: dx = dt = 1, rho_0 = 1, c_s^2 = 1/3. Boxes are periodic
+ *   along every axis without walls (psm_box_desc.walls_x, walls_y, walls_z).
  * - Cells: index n = x + nx*(y + ny*z); cell (i,j,k) has its centre at
  *   (i+1/2, j+1/2, k+1/2) in [0,nx) x [0,ny) x [0,nz).
  * - PDFs: canonical layout [19][N] (q-major), FP64, pre-collision state
@@ -82,6 +82,9 @@ typedef struct psm_box_desc {
     double face_rho[2];     /* pressure faces: density rho_w > 0; anti-bounce-back
                                f_qbar = -f~_q + 2 w_q (rho_w + 4.5 (c_q.u)^2 - 1.5 u.u), u the boundary
                                cell's post-collision velocity */
+    int walls_x, walls_y;   /* 1: resting no-slip walls at x = 0 and x = nx (y = 0, y = ny) instead of
+                               periodicity (half-way bounce-back); they take precedence over a z face
+                               for a population crossing both */
 } psm_box_desc;
 
 typedef struct psm_ctx psm_ctx;
@@ -125,8 +128,8 @@ int psm_get_macroscopic(psm_ctx* ctx, int box, double* rho, double* u);
 /* Set the spheres of box `box` (Sec. 3.1.1: positions, radii, then linear and
  * angular velocities). Host arrays, row-major: x (n,3), r (n), U (n,3),
  * omega (n,3) (NULL omega = 0); they are copied before the call returns.
- * Positions are wrapped into the box. Radii must lie in [1, max_radius]; in a
- * box with walls every centre needs r + 1 <= z <= nz - r - 1. The
+ * Positions are wrapped into the box. Radii must lie in [1, max_radius]; along
+ * an axis with walls every centre needs r + 1 <= x_a <= n_a - r - 1. The
  * library computes f(r) of eq. (26) in FP64 and uploads through pinned staging
  * (asynchronous). When positions or radii differ from the previous call it
  * rebuilds the per-tile candidate lists, which synchronises and returns

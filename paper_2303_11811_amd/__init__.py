@@ -39,7 +39,8 @@ class psm_box_desc(ctypes.Structure):
                 ("max_particles", ctypes.c_int), ("max_radius", ctypes.c_double),
                 ("mapping", ctypes.c_int), ("subsample_n", ctypes.c_int),
                 ("walls_z", ctypes.c_int), ("wall_u", (ctypes.c_double * 3) * 2),
-                ("face_type", ctypes.c_int * 2), ("face_rho", ctypes.c_double * 2)]
+                ("face_type", ctypes.c_int * 2), ("face_rho", ctypes.c_double * 2),
+                ("walls_x", ctypes.c_int), ("walls_y", ctypes.c_int)]
 
 
 _lib = None
@@ -111,7 +112,7 @@ def _dptr(a):
 def make_desc(nx, ny, nz, tau, fext=(0.0, 0.0, 0.0), max_particles=0, max_radius=1.0,
               mapping=PSM_MAP_LINEAR, subsample_n=4, walls_z=False,
               wall_u=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)), face_type=(PSM_FACE_VELOCITY, PSM_FACE_VELOCITY),
-              face_rho=(1.0, 1.0)) -> psm_box_desc:
+              face_rho=(1.0, 1.0), walls_x=False, walls_y=False) -> psm_box_desc:
     d = psm_box_desc()
     d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
     d.tau = float(tau)
@@ -127,6 +128,7 @@ def make_desc(nx, ny, nz, tau, fext=(0.0, 0.0, 0.0), max_particles=0, max_radius
             d.wall_u[w][a] = float(wall_u[w][a])
         d.face_type[w] = int(face_type[w])
         d.face_rho[w] = float(face_rho[w])
+    d.walls_x, d.walls_y = int(bool(walls_x)), int(bool(walls_y))
     return d
 
 
@@ -419,4 +421,4 @@ def desc_from_spec(spec, max_particles=None, max_radius=None):
     rmax = (float(np.max(spec.r)) if len(spec.r) else 1.0) if max_radius is None else max_radius
     return make_desc(*spec.dims, spec.tau, spec.fext, max_particles=n, max_radius=max(rmax, 1.0),
                      mapping=spec.mapping, subsample_n=spec.nsub, walls_z=spec.walls_z, wall_u=spec.wall_u,
-                     face_type=spec.face_type, face_rho=spec.face_rho)
+                     face_type=spec.face_type, face_rho=spec.face_rho, walls_x=spec.walls_x, walls_y=spec.walls_y)

@@ -102,6 +102,8 @@ static int validate(const psm_box_desc* boxes, int nbox, int storage) {
             if (!std::isfinite(d.fext[a])) return fail(PSM_EINVAL, "box %d: non-finite body force", b);
         if (d.max_particles < 0) return fail(PSM_EINVAL, "box %d: max_particles < 0", b);
         if (d.walls_z != 0 && d.walls_z != 1) return fail(PSM_EINVAL, "box %d: walls_z must be 0 or 1", b);
+        if ((d.walls_x != 0 && d.walls_x != 1) || (d.walls_y != 0 && d.walls_y != 1))
+            return fail(PSM_EINVAL, "box %d: walls_x and walls_y must be 0 or 1", b);
         for (int w = 0; w < 2 && d.walls_z; ++w) {
             for (int a = 0; a < 3; ++a)
                 if (!std::isfinite(d.wall_u[w][a])) return fail(PSM_EINVAL, "box %d: non-finite wall velocity", b);
@@ -424,6 +426,7 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
         bx.reach = 0.8660254037844386 * (1.0 - 1.0 / bx.nsub) + 1e-9;
         bx.rho_p = 1.0;
         bx.walls = d.walls_z;
+        bx.walls_xy = (d.walls_x ? 1 : 0) | (d.walls_y ? 2 : 0);
         for (int w = 0; w < 2; ++w) {
             bx.face_type[w] = d.walls_z ? d.face_type[w] : FACE_VELOCITY;
             bx.face_rho[w] = bx.face_type[w] == FACE_PRESSURE ? d.face_rho[w] : 1.0;
@@ -587,8 +590,11 @@ extern "C" int psm_set_particles(psm_ctx* c, int box, int n, const double* x, co
     for (int p = 0; p < n; ++p) {
         if (!(r[p] >= 1.0 && r[p] <= d.max_radius))
             return fail(PSM_EINVAL, "particle %d: radius %g outside [1, %g]", p, r[p], d.max_radius);
-        if (d.walls_z && !(x[3 * p + 2] >= r[p] + 1.0 && x[3 * p + 2] <= d.nz - r[p] - 1.0))
-            return fail(PSM_EINVAL, "particle %d: centre closer than r + 1 to a wall", p);
+        const int walled[3] = {d.walls_x, d.walls_y, d.walls_z};
+        const int dims3[3] = {d.nx, d.ny, d.nz};
+        for (int a = 0; a < 3; ++a)
+            if (walled[a] && !(x[3 * p + a] >= r[p] + 1.0 && x[3 * p + a] <= dims3[a] - r[p] - 1.0))
+                return fail(PSM_EINVAL, "particle %d: centre closer than r + 1 to a wall", p);
         for (int a = 0; a < 3; ++a) {
             if (!std::isfinite(x[3 * p + a]) || !std::isfinite(U[3 * p + a]) ||
                 (omega && !std::isfinite(omega[3 * p + a])))

@@ -57,6 +57,7 @@ struct BoxDev {
     // minus that population plus 2 w_q (face_rho[w] + 4.5 (c_q.u)^2 - 1.5 u.u)
     // with u the cell's post-collision velocity (anti-bounce-back).
     int walls;
+    int walls_xy;                   // bit 0: resting walls at x = 0, nx; bit 1: at y = 0, ny
     int face_type[2];               // FACE_VELOCITY or FACE_PRESSURE
     double face_rho[2];
     double bw[2][NQ];

@@ -274,6 +274,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
             int c = xx + nxl * yy;
             return (unsigned)(((c / BLK) * (NQ * BLK) + (c % BLK)) * (int)sizeof(T));
         };
+        // lanes next to a resting side wall (x = 0, nx - 1; y = 0, ny - 1): bits 0-3
+        const int edge = !lane_ok || !bx.walls_xy ? 0
+                         : (((bx.walls_xy & 1) && xs == 0) ? 1 : 0) | (((bx.walls_xy & 1) && xs == nx - 1) ? 2 : 0) |
+                               (((bx.walls_xy & 2) && ys == 0) ? 4 : 0) | (((bx.walls_xy & 2) && ys == ny - 1) ? 8 : 0);
+        const bool edge_wave = __ballot(edge != 0) != 0ull;
         const unsigned o00 = inplane(xs, ys), om0 = inplane(xm, ys), op0 = inplane(xp, ys);
         const unsigned o0m = inplane(xs, ym), o0p = inplane(xs, yp);
         const unsigned omm = inplane(xm, ym), opp = inplane(xp, yp), omp = inplane(xm, yp), opm = inplane(xp, ym);
@@ -420,6 +425,17 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
                         f[5] = fb[0]; f[11] = fb[1]; f[14] = fb[2]; f[15] = fb[3]; f[18] = fb[4];
                     } else {
                         f[6] = fb[0]; f[12] = fb[1]; f[13] = fb[2]; f[16] = fb[3]; f[17] = fb[4];
+                    }
+                }
+                if (edge_wave && edge) {
+                    // resting side walls (they win over a z face): a population
+                    // pulled from behind a wall is the one this cell sent
+                    // against it last step
+#pragma unroll
+                    for (int q = 1; q < NQ; ++q) {
+                        const bool hit = (CX[q] == 1 && (edge & 1)) || (CX[q] == -1 && (edge & 2)) ||
+                                         (CY[q] == 1 && (edge & 4)) || (CY[q] == -1 && (edge & 8));
+                        if (hit) f[q] = S::loadb(sbz + inv_dir(q) * QB, o00, kp.h_inv);
                     }
                 }
 
@@ -734,6 +750,11 @@ __device__ inline int face_of(const BoxDev& bx, int zz) {
     return !bx.walls ? -1 : (zz < 0 ? 0 : (zz >= bx.nz ? 1 : -1));
 }
 
+// True if the neighbour at (xx, yy) lies behind a resting side wall.
+__device__ inline bool behind_side_wall(const BoxDev& bx, int xx, int yy) {
+    return ((bx.walls_xy & 1) && (xx < 0 || xx >= bx.nx)) || ((bx.walls_xy & 2) && (yy < 0 || yy >= bx.ny));
+}
+
 // Post-collision velocity of a cell from its own 19 stored slots (slot q of
 // cell x holds the value it sent in direction q), in S::to_f64 units.
 template <class S>
@@ -761,6 +782,8 @@ __device__ inline double abb_value(int q, double s_opp, double rho, const double
 // population the cell sent against it (direction inv_dir(q)).
 template <class S>
 __device__ inline double pull_value(const BoxDev& bx, const typename S::T* g, int q, int x, int y, int z, float inv) {
+    if (behind_side_wall(bx, x - CX[q], y - CY[q]))   // resting side wall: bounce-back
+        return S::to_f64(g[pdf_index(bx, inv_dir(q), x, y, z)], inv);
     int zs = z - CZ[q];
     int w = face_of(bx, zs);
     if (w >= 0) {
@@ -796,7 +819,9 @@ __device__ inline void store_cell_slots(const BoxDev& bx, typename S::T* g, int 
     for (int q = 0; q < NQ; ++q) {
         int zd = z + CZ[q];
         int w = face_of(bx, zd);
-        if (w < 0) {
+        if (behind_side_wall(bx, x + CX[q], y + CY[q])) {
+            sl[q] = canon(inv_dir(q), self);
+        } else if (w < 0) {
             int xd = x + CX[q], yd = y + CY[q];
             xd = xd < 0 ? xd + bx.nx : (xd >= bx.nx ? xd - bx.nx : xd);
             yd = yd < 0 ? yd + bx.ny : (yd >= bx.ny ? yd - bx.ny : yd);
@@ -816,7 +841,7 @@ __device__ inline void store_cell_slots(const BoxDev& bx, typename S::T* g, int 
                 u[0] += sl[q] * CX[q]; u[1] += sl[q] * CY[q]; u[2] += sl[q] * CZ[q];
             }
             for (int q = 0; q < NQ; ++q)
-                if (face_of(bx, z + CZ[q]) == pface)
+                if (face_of(bx, z + CZ[q]) == pface && !behind_side_wall(bx, x + CX[q], y + CY[q]))
                     sl[q] = abb_value(q, canon(inv_dir(q), self), bx.face_rho[pface], u);
         }
     }
@@ -959,7 +984,9 @@ __global__ __launch_bounds__(256) void k_stats_partial(BoxDev bx, int parity, fl
             double v = S::to_f64(g[pdf_index(bx, q, x, y, z)], inv);
             int d = q;
             int w = face_of(bx, z + CZ[q]);
-            if (w >= 0) {
+            if (behind_side_wall(bx, x + CX[q], y + CY[q])) {
+                d = inv_dir(q);
+            } else if (w >= 0) {
                 d = inv_dir(q);
                 v = bx.face_type[w] == FACE_PRESSURE
                         ? abb_value(d, v, S::DEV ? bx.face_rho[w] - 1.0 : bx.face_rho[w], uc)

@@ -199,6 +199,8 @@ class BoxSpec:
     wall_u: tuple = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))   # bottom and top velocity-face velocities
     face_type: tuple = (0, 0)      # 0 velocity face (bounce-back), 1 pressure face (anti-bounce-back)
     face_rho: tuple = (1.0, 1.0)   # pressure-face densities
+    walls_x: bool = False          # resting no-slip walls at x = 0 and x = nx
+    walls_y: bool = False          # resting no-slip walls at y = 0 and y = ny
 
     @property
     def N(self):

@@ -10,7 +10,8 @@ import paper_2303_11811_amd as psm
 
 def oracle_box(spec):
     return oracle.Box(*spec.dims, tau=spec.tau, fext=spec.fext, mapping=spec.mapping, nsub=spec.nsub,
-                      walls_z=spec.walls_z, wall_u=spec.wall_u, face_type=spec.face_type, face_rho=spec.face_rho)
+                      walls_z=spec.walls_z, wall_u=spec.wall_u, face_type=spec.face_type, face_rho=spec.face_rho,
+                      walls_x=spec.walls_x, walls_y=spec.walls_y)
 
 
 def initial_f(spec):

@@ -207,3 +207,71 @@ def test_pressure_outflow_state_roundtrip_and_plug_flow():
     f3, *_, eng = run_engine(rest, 7000, launch=(16, 16, 2, 0))
     eng.close()
     assert np.max(np.abs(f3 - fp)) < 1e-12
+
+
+def _bed(dims, n, seed, tau=0.7, U=(0.0, 0.0, 0.01), rho_out=1.0):
+    """A small fluidized-bed-like box: resting side walls in x and y, a
+    velocity inflow at z = 0, a pressure outflow at z = nz, spheres at least
+    r + 1 from every wall."""
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(2.5, 4.0, n)
+    L = np.asarray(dims, dtype=float)
+    x = (r + 1.0)[:, None] + rng.random((n, 3)) * (L[None, :] - 2.0 * (r + 1.0)[:, None])
+    base = inputs.random_small(dims, 0, (2, 3), seed=seed, tau=tau)
+    return inputs.BoxSpec(dims=dims, tau=tau, fext=(0.0, 0.0, -2e-6), x=x, r=r,
+                          U=inputs.uniform_velocities(rng, n, 0.01), Om=inputs.uniform_velocities(rng, n, 0.002),
+                          u0=0.5 * base.u0, walls_z=True, wall_u=(U, (0.0, 0.0, 0.0)), face_type=(0, 1),
+                          face_rho=(1.0, rho_out), walls_x=True, walls_y=True)
+
+
+@pytest.mark.parametrize("dims,launch", [((30, 22, 26), (32, 8, 4, 0)), ((41, 27, 19), (64, 4, 8, 3)),
+                                         ((20, 36, 24), (16, 16, 2, 2))])
+def test_side_walls_bed_parity_fp64(dims, launch):
+    spec = _bed(dims, 4, seed=sum(dims), rho_out=1.001)
+    print(f"[case] bed fp64 dims={dims} launch={launch}", flush=True)
+    ref = run_oracle(spec, 15)
+    f, F, T, B, pid, eng = run_engine(spec, 15, launch=launch)
+    mass, mom, _ = eng.get_stats(0)
+    eng.close()
+    assert_pdfs_close(f, ref.f, 1e-12)
+    assert_forces_close(F, ref.F, ref.A)
+    assert_forces_close(T, ref.T, ref.A, lever=spec.r.max() + 1)
+    c, _, _ = oracle.lattice()
+    assert abs(mass - ref.f.sum()) <= 1e-12 * ref.f.sum()
+    mref = np.array([(ref.f * c[:, a:a + 1]).sum() for a in range(3)])
+    assert np.all(np.abs(mom - mref) <= 1e-12 * ref.f.sum())
+
+
+@pytest.mark.parametrize("storage,tol_u", [(psm.PSM_FP32DEV, 2e-5), (psm.PSM_FP16DEV, 3e-3)])
+def test_side_walls_bed_deviation_forms(storage, tol_u):
+    spec = _bed((24, 20, 18), 2, seed=12)
+    ref = run_oracle(spec, 40)
+    f, *_, eng = run_engine(spec, 40, storage=storage)
+    eng.close()
+    box = oracle.Box(*spec.dims, tau=spec.tau)
+    _, u_ref = oracle.macroscopic(box, ref.f)
+    _, u = oracle.macroscopic(box, f)
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < tol_u
+
+
+def test_side_walls_roundtrip_and_duct_profile():
+    spec = _bed((14, 10, 8), 0, seed=6)
+    f0 = initial_f(spec) + 1e-3 * np.random.default_rng(7).standard_normal((19, spec.N))
+    eng = make_engine([spec])
+    eng.set_pdfs(0, f0)
+    f1 = eng.get_pdfs(0).cpu().numpy()
+    eng.close()
+    assert np.max(np.abs(f1 - f0)) <= 1e-15
+    # body-force flow along z between x walls: the half-way bounce-back closed form
+    H, tau, g = 10, 0.8, 1e-5
+    nu = (tau - 0.5) / 3.0
+    duct = inputs.BoxSpec(dims=(H, 4, 4), tau=tau, fext=(0.0, 0.0, g), walls_x=True)
+    steps = int(40 * H * H / (math.pi ** 2 * nu)) + 200
+    f, *_, eng = run_engine(duct, steps, launch=(16, 16, 4, 0))
+    _, u = eng.get_macroscopic(0)
+    u = u.cpu().numpy()
+    eng.close()
+    x = np.arange(H) + 0.0
+    exact = g / (2 * nu) * (x + 0.5) * (H - 0.5 - x) + 2 * g / (3 * nu) * ((tau - 0.5) ** 2 - 3.0 / 16.0)
+    prof = u[2].reshape(4, 4, H)[0, 0, :]
+    assert np.max(np.abs(prof - exact)) / exact.max() < 1e-9

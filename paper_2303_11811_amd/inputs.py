@@ -129,18 +129,23 @@ def rsa_spheres(dims, radii, rng, max_attempts_per_sphere=20000, gap=0.0):
 
 def jittered_lattice_spheres(dims, n, r, rng):
     """n non-overlapping spheres of radius r for dense packings (where random
-    sequential addition slows down near jamming): the smallest cubic lattice
-    with at least n sites, a seeded choice of n sites, each centre jittered
-    uniformly by up to half the gap between neighbouring spheres per axis.
-    Needs a lattice spacing >= 2r."""
+    sequential addition slows down near jamming): the coarsest near-cubic
+    lattice with at least n sites (else the finest with spacing >= 2r along
+    every axis), a seeded choice of n sites, each centre jittered uniformly
+    by up to half the gap between neighbouring spheres per axis."""
     L = np.asarray(dims, dtype=np.float64)
-    m = int(math.ceil((n * np.prod(L) / L.min() ** 3) ** (1.0 / 3.0)))
+    m = int(math.ceil((n * L.min() ** 3 / np.prod(L)) ** (1.0 / 3.0)))
     counts = np.maximum((m * L / L.min()).astype(int), 1)
     while np.prod(counts) < n:
         counts[np.argmin(L / counts)] += 1
     a = L / counts
     if np.any(a < 2.0 * r):
-        raise ValueError("solid fraction too high for a jittered lattice")
+        # the near-cubic lattice is too fine along some axis: take the most
+        # sites that keep a spacing of 2r along every axis
+        counts = np.floor(L / (2.0 * r)).astype(int)
+        if np.prod(counts) < n:
+            raise ValueError("solid fraction too high for a jittered lattice")
+        a = L / counts
     sites = np.stack(np.meshgrid(*[np.arange(c) for c in counts], indexing="ij"), -1).reshape(-1, 3)
     pick = rng.choice(len(sites), n, replace=False)
     jit = (rng.random((n, 3)) * 2.0 - 1.0) * (a - 2.0 * r) / 2.0
@@ -296,3 +301,42 @@ def random_small(dims, nparticles, radius_range, seed, tau=0.7, fext=(0.0, 0.0, 
     rho0 = 1.0 + (rng.random(N) * 2 - 1) * 1e-3
     return BoxSpec(dims=tuple(int(d) for d in dims), tau=tau, fext=tuple(fext), mapping=mapping,
                    x=x, r=r, U=U, Om=Om, u0=u0, rho0=rho0)
+
+
+def fluidized_bed(case="dilute", seed=5, tau=0.65, rho_p=1.1, galileo=8.9, re_p=1.0):
+    """Synthetic stand-in for the paper's fluidized bed (Sec. 4.1): a
+    500 x 200 x 800 box (z vertical) with resting no-slip walls in x and y,
+    a velocity inflow at z = 0 and a pressure outflow (density 1) at z = 800,
+    FP64, spheres of diameter 20 and density ratio 1.1: 627 (dilute, about
+    3.3 % solid) placed by random sequential addition, or 8073 (dense, about
+    42 %) on a jittered lattice, every centre at least r + 1 from the walls,
+    at rest. The inflow speed follows from the particle Reynolds number
+    U d / nu = re_p and the sphere's gravity-minus-buoyancy acceleration from
+    the Galileo number sqrt((rho_p - 1) g d^3) / nu = galileo, with
+    nu = (tau - 1/2)/3. Returns (spec, density ratio, external acceleration)."""
+    rng = np.random.default_rng(seed)
+    dims = (500, 200, 800)
+    r = 10.0
+    L = np.asarray(dims, dtype=np.float64)
+    if case == "dilute":
+        inner = L - 2.0 * (r + 1.0)
+        x, rr = rsa_spheres(tuple(inner), np.full(627, r), rng)
+        x = x + (r + 1.0)
+    elif case == "dense":
+        # lattice centres 1 + (k + 1/2) a with a >= 2r stay r + 1 from the walls
+        x, rr = jittered_lattice_spheres(tuple(L - 2.0), 8073, r, rng)
+        x = x + 1.0
+    else:
+        raise ValueError(case)
+    nu = (tau - 0.5) / 3.0
+    d = 2.0 * r
+    u_in = re_p * nu / d
+    g = (galileo * nu) ** 2 / ((rho_p - 1.0) * d ** 3)
+    accel = (0.0, 0.0, -g * (1.0 - 1.0 / rho_p))
+    N = int(np.prod(dims))
+    u0 = np.zeros((3, N))
+    u0[2] = u_in
+    spec = BoxSpec(dims=dims, tau=tau, fext=(0.0, 0.0, 0.0), mapping=0, x=x, r=rr, U=np.zeros_like(x),
+                   Om=np.zeros_like(x), u0=u0, walls_z=True, wall_u=((0.0, 0.0, u_in), (0.0, 0.0, 0.0)),
+                   face_type=(0, 1), face_rho=(1.0, 1.0), walls_x=True, walls_y=True)
+    return spec, rho_p, accel

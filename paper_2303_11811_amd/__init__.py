@@ -297,8 +297,9 @@ class Engine:
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
-            psm_destroy(self.ctx)
+            psm_destroy(self.ctx)   # waits for the stream
             self.ctx = None
+        self.workspace = None
 
     def __del__(self):
         try:

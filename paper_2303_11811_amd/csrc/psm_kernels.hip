@@ -958,7 +958,7 @@ __global__ void k_macroscopic(BoxDev bx, int parity, double* __restrict__ rho, d
 
 // Dense two-slot solid fractions of one box (readout and overflow count),
 // through the same candidate lists and mapping function as the step kernel.
-__global__ void k_map_dense(BoxDev bx, int box_tile_base_unused, Particles P, const int* __restrict__ tile_off,
+__global__ void k_map_dense(BoxDev bx, Particles P, const int* __restrict__ tile_off,
                             const int* __restrict__ tile_pid, TileShape ts, double* __restrict__ B,
                             int* __restrict__ pid, unsigned long long* dropped) {
     long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1238,7 +1238,7 @@ hipError_t launch_macroscopic(int storage, const BoxDev& bx, int parity, double*
 
 hipError_t launch_map_dense(const BoxDev& bx, const Particles& P, const int* tile_off, const int* tile_pid,
                             TileShape ts, double* B, int* pid, unsigned long long* dropped, hipStream_t st) {
-    hipLaunchKernelGGL(k_map_dense, dim3(blocks_for(bx.N, 256)), dim3(256), 0, st, bx, 0, P, tile_off, tile_pid, ts,
+    hipLaunchKernelGGL(k_map_dense, dim3(blocks_for(bx.N, 256)), dim3(256), 0, st, bx, P, tile_off, tile_pid, ts,
                        B, pid, dropped);
     return hipGetLastError();
 }

@@ -179,7 +179,10 @@ int psm_set_dynamics(psm_ctx* ctx, int box, double density_ratio, const double* 
 
 /* Advance every sphere of every box by one update of `scheme` (psm_scheme)
  * with time step dt > 0, using the force and torque of the last executed
- * step; positions are wrapped into the box. Then rebuild the per-tile
+ * step; positions are wrapped into the box along periodic axes, and along an
+ * axis with walls a centre leaving [r + 1, n_a - r - 1] is mirrored back with
+ * its velocity component reversed (elastic contact; no sphere-sphere
+ * contact is modelled). Then rebuild the per-tile
  * candidate lists on the device. Asynchronous: nothing is read back. If the
  * moved spheres put more than 64 candidates into a tile, the lists are cut
  * there (the step stays in bounds but its results are not valid) and the next

@@ -81,7 +81,7 @@ def _load():
                                  _D, _D, _D, _D, _I]
         lib.psmo_run.restype = ctypes.c_longlong
         lib.psmo_integrate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D, _D,
-                                       _D, _D, _D, _D, _D, _D, _D, _D, ctypes.c_int]
+                                       _I, _D, _D, _D, _D, _D, _D, _D, _D, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -283,8 +283,9 @@ def integrate(box: Box, dyn: Dynamics, F, T, dt=1.0, scheme=VERLET, rho_p=1.0, a
     F = _f64(F, (-1, 3))
     T = _f64(T, (-1, 3))
     L = np.array([box.nx, box.ny, box.nz], dtype=np.float64)
+    walls = np.array([box.walls_x, box.walls_y, box.walls_z], dtype=np.int32)
     a = _f64(accel, (3,))
-    _load().psmo_integrate(len(dyn.r), int(scheme), float(dt), float(rho_p), _dp(a), _dp(L), _dp(dyn.r),
+    _load().psmo_integrate(len(dyn.r), int(scheme), float(dt), float(rho_p), _dp(a), _dp(L), _ip(walls), _dp(dyn.r),
                            _dp(dyn.x), _dp(dyn.U), _dp(dyn.Om), _dp(F), _dp(T), _dp(dyn.Fprev),
                            _dp(dyn.Tprev), int(dyn.have_prev))
     if scheme == VERLET:

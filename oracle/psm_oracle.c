@@ -539,7 +539,11 @@ long long psmo_run(const psmo_box *b, int nsteps, int np, const double *x, const
  * step with that step's force F (taken at the positions x it used):
  *   if have_prev:  U  += dt/(2m) (F_prev + F),  Om += dt/(2I) (T_prev + T)
  *   then           x  += dt U + dt^2/(2m) F,    F_prev = F, T_prev = T.
- * Positions are wrapped into [0, L) afterwards. Arrays (n,3) row-major,
+ * Positions are wrapped into [0, L) afterwards along periodic axes; along an
+ * axis with walls (walls[a] != 0) a centre that leaves [r + 1, L - r - 1] is
+ * mirrored back and its velocity component reversed (an elastic contact that
+ * keeps the one-cell gap the solid-fraction mapping needs; the paper's DEM
+ * contact with the bounding planes is out of scope). Arrays (n,3) row-major,
  * updated in place. */
 static double wrap_coord(double v, double L)
 {
@@ -550,8 +554,8 @@ static double wrap_coord(double v, double L)
 }
 
 void psmo_integrate(int n, int scheme, double dt, double rho_p, const double *accel, const double *Lbox,
-                    const double *r, double *x, double *U, double *Om, const double *F, const double *T,
-                    double *Fprev, double *Tprev, int have_prev)
+                    const int *walls, const double *r, double *x, double *U, double *Om, const double *F,
+                    const double *T, double *Fprev, double *Tprev, int have_prev)
 {
     const double pi = 3.14159265358979323846;
     for (int p = 0; p < n; ++p) {
@@ -579,6 +583,22 @@ void psmo_integrate(int n, int scheme, double dt, double rho_p, const double *ac
                 Tprev[3 * p + a] = Tt[a];
             }
         }
-        for (int a = 0; a < 3; ++a) x[3 * p + a] = wrap_coord(x[3 * p + a], Lbox[a]);
+        for (int a = 0; a < 3; ++a) {
+            if (!walls[a]) {
+                x[3 * p + a] = wrap_coord(x[3 * p + a], Lbox[a]);
+                continue;
+            }
+            /* elastic contact with the walls of this axis, one cell before
+               the sphere reaches them: mirror the centre back into
+               [r + 1, L - r - 1] and reverse the normal velocity */
+            double lo = r[p] + 1.0, hi = Lbox[a] - r[p] - 1.0;
+            if (x[3 * p + a] < lo) {
+                x[3 * p + a] = 2.0 * lo - x[3 * p + a];
+                U[3 * p + a] = -U[3 * p + a];
+            } else if (x[3 * p + a] > hi) {
+                x[3 * p + a] = 2.0 * hi - x[3 * p + a];
+                U[3 * p + a] = -U[3 * p + a];
+            }
+        }
     }
 }

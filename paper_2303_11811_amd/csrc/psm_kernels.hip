@@ -1063,8 +1063,10 @@ __global__ __launch_bounds__(256) void k_stream_copy(const double2* __restrict__
 //   Verlet (eqs. 15-16), once after each fluid step: complete the velocity
 //   with the previous and the new force (skipped until a previous force
 //   exists), then advance the position with the new one.
-// Positions are wrapped into [0, L). No fused multiply-add, so that the
-// update is reproducible bit for bit.
+// Positions are wrapped into [0, L) along periodic axes; along an axis with
+// walls a centre leaving [r + 1, L - r - 1] is mirrored back and its velocity
+// component reversed (elastic contact keeping the mapping's one-cell gap).
+// No fused multiply-add, so that the update is reproducible bit for bit.
 template <int SCHEME>
 __global__ __launch_bounds__(256) void k_integrate(IntParams ip) {
 #pragma clang fp contract(off)
@@ -1100,10 +1102,20 @@ __global__ __launch_bounds__(256) void k_integrate(IntParams ip) {
             fp[3 + a] = T;
         }
         const double L = bx.L[a];
-        double w = x - L * floor(x / L);
-        if (w >= L) w -= L;
-        if (w < 0.0) w = 0.0;
-        pos[a][p] = w;
+        const bool walled = a == 2 ? bx.walls != 0 : (bx.walls_xy & (1 << a)) != 0;
+        if (walled) {
+            // elastic contact one cell before the walls: mirror the centre back
+            // into [r + 1, L - r - 1] and reverse the normal velocity
+            const double lo = r + 1.0, hi = L - r - 1.0;
+            if (x < lo) { x = 2.0 * lo - x; U = -U; }
+            else if (x > hi) { x = 2.0 * hi - x; U = -U; }
+        } else {
+            double w = x - L * floor(x / L);
+            if (w >= L) w -= L;
+            if (w < 0.0) w = 0.0;
+            x = w;
+        }
+        pos[a][p] = x;
         vel[a][p] = U;
         ang[a][p] = W;
     }

@@ -105,3 +105,20 @@ def test_positions_wrap_into_the_box():
     oracle.integrate(box, dyn, np.zeros((2, 3)), np.zeros((2, 3)), scheme=oracle.EULER)
     assert np.allclose(dyn.x, [[0.2, 29.7, 0.05], [39.5, 0.01, 10.0]], rtol=0, atol=1e-12)
     assert np.all(dyn.x >= 0) and np.all(dyn.x < np.array([40, 30, 20]))
+
+
+def test_elastic_contact_with_walls():
+    """Along an axis with walls a sphere keeps one cell of gap: a centre that
+    passes r + 1 (or L - r - 1) is mirrored back and the normal velocity
+    reverses; the other axes stay periodic."""
+    box = oracle.Box(40, 30, 50, tau=0.6, walls_z=True, walls_x=True)
+    r = 4.0
+    dyn = oracle.Dynamics([[5.2, 29.5, 5.3], [34.7, 3.0, 44.6]], [r, r],
+                          [[-0.5, 0.8, -0.6], [0.4, -0.1, 0.7]], np.zeros((2, 3)))
+    oracle.integrate(box, dyn, np.zeros((2, 3)), np.zeros((2, 3)), scheme=oracle.EULER)
+    # sphere 0: x 5.2 - 0.5 = 4.7 < 5 -> 5.3, y wraps (periodic), z 5.3 - 0.6 = 4.7 -> 5.3
+    assert np.allclose(dyn.x[0], [5.3, 0.3, 5.3], rtol=0, atol=1e-12)
+    assert np.allclose(dyn.U[0], [0.5, 0.8, 0.6])
+    # sphere 1: x 35.1 > 35 -> 34.9, z 45.3 > 45 -> 44.7
+    assert np.allclose(dyn.x[1], [34.9, 2.9, 44.7], rtol=0, atol=1e-12)
+    assert np.allclose(dyn.U[1], [-0.4, -0.1, -0.7])

@@ -5,8 +5,9 @@
 // per-tile candidate lists, the per-(tile, sphere) force partials and a few
 // scratch words. Particle uploads go through pinned staging. The time step
 // of Sec. 3.1 of the paper (mapping -> PSM kernel -> force reduction) is one
-// persistent fused launch plus one small reduction launch; 10-step runs can
-// be replayed from captured HIP graphs.
+// fused launch over the tiles of all boxes plus one small reduction launch;
+// 10-step runs can be replayed from captured HIP graphs. The sphere update of
+// Sec. 2.2.2 and the re-binning it needs run on the device as well.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -214,26 +214,34 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
         U = U + F / mass[:, None]
         Om = Om + T / inertia[:, None]
 
-    def one_device():
-        eng.step(1)
-        eng.integrate(1.0, psm.PSM_EULER)
-
     if device:
+        # kernel time from an eager timed pass, wall time from graph replays
+        # of 10 (step + update) pairs with the host out of the loop
         eng.set_particles(0, x, spec.r, U, Om)
         eng.set_dynamics(0, 2.5)
-        one = one_device   # noqa: F811
-    for _ in range(warmup):
-        one()
-    eng.synchronize()
-    eng.reset_timing()
-    eng.set_timing(True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        one()
-    if device:
+        eng.reset_timing()
+        eng.set_timing(True)
+        eng.run(warmup + 10, 1.0, psm.PSM_EULER)
+        nl, kms = eng.get_timing()
+        eng.set_timing(False)
+        eng.set_graph(True)
+        eng.run(10, 1.0, psm.PSM_EULER)
+        eng.synchronize()
+        t0 = time.perf_counter()
+        eng.run(steps, 1.0, psm.PSM_EULER)
         eng.get_forces(0)   # synchronises; reports a device-side list overflow
-    dt = time.perf_counter() - t0
-    nl, kms = eng.get_timing()
+        dt = time.perf_counter() - t0
+    else:
+        for _ in range(warmup):
+            one()
+        eng.synchronize()
+        eng.reset_timing()
+        eng.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            one()
+        dt = time.perf_counter() - t0
+        nl, kms = eng.get_timing()
     _, _, ov = eng.get_stats(0)
     eng.close()
     torch.cuda.empty_cache()
@@ -243,8 +251,8 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
             "mlups": spec.N * steps / dt / 1e6, "ms_per_step": step_ms, "kernel_ms": kern,
             "coupling_overhead_frac": (step_ms - kern) / step_ms, "launch": list(shape),
             "slot_overflows_last_map": ov,
-            "particle_update": "device explicit Euler (psm_integrate)" if device else
-                               "host explicit Euler, upload, read-back"}
+            "particle_update": "device explicit Euler (psm_run: graphs of 10 step + update pairs)" if device
+                               else "host explicit Euler, upload, read-back"}
 
 
 def run_fluidized_bed(psm, torch, inputs, case, steps=200, warmup=5):
@@ -265,22 +273,19 @@ def run_fluidized_bed(psm, torch, inputs, case, steps=200, warmup=5):
     del u0
     eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
     eng.set_dynamics(0, rho_p, accel)
-
-    def one():
-        eng.step(1)
-        eng.integrate(1.0, psm.PSM_VERLET)
-
-    for _ in range(warmup):
-        one()
-    eng.synchronize()
+    # kernel time from an eager timed pass, wall time from graph replays
     eng.reset_timing()
     eng.set_timing(True)
+    eng.run(warmup + 10, 1.0, psm.PSM_VERLET)
+    nl, kms = eng.get_timing()
+    eng.set_timing(False)
+    eng.set_graph(True)
+    eng.run(10, 1.0, psm.PSM_VERLET)
+    eng.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        one()
+    eng.run(steps, 1.0, psm.PSM_VERLET)
     F, _ = eng.get_forces(0)   # synchronises; reports a device-side list overflow
     dt = time.perf_counter() - t0
-    nl, kms = eng.get_timing()
     _, _, ov = eng.get_stats(0)
     eng.close()
     torch.cuda.empty_cache()
@@ -289,7 +294,7 @@ def run_fluidized_bed(psm, torch, inputs, case, steps=200, warmup=5):
             "mlups": spec.N * steps / dt / 1e6, "ms_per_step": dt * 1e3 / steps, "kernel_ms": kern,
             "roofline_frac": spec.N * BYTES_PER_CELL[0] / (kern * 1e-3) / 1e9 / HBM_PEAK_GBPS,
             "launch": list(shape), "slot_overflows_last_map": ov, "forces_finite": bool(np.all(np.isfinite(F))),
-            "particle_update": "device velocity Verlet (psm_integrate)"}
+            "particle_update": "device velocity Verlet (psm_run: graphs of 10 step + update pairs)"}
 
 
 def cpu_baseline(inputs, n, steps):

@@ -191,6 +191,12 @@ int psm_set_dynamics(psm_ctx* ctx, int box, double density_ratio, const double* 
  * restarts velocity Verlet (its first update has no previous force). */
 int psm_integrate(psm_ctx* ctx, double dt, int scheme);
 
+/* nsteps times (psm_step(ctx, 1) then psm_integrate(ctx, dt, scheme)), with
+ * the host out of the loop: with graphs enabled (psm_set_graph), runs of 10
+ * such pairs replay a captured HIP graph (recaptured when dt or scheme
+ * change). Asynchronous; errors as psm_integrate. */
+int psm_run(psm_ctx* ctx, int nsteps, double dt, int scheme);
+
 /* Current positions x, velocities U and angular velocities omega of the
  * spheres of box `box` (host (n,3) each, any may be NULL). Synchronises;
  * reports a device-side list overflow as psm_integrate describes. */

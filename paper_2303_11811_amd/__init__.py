@@ -74,6 +74,7 @@ _SIGS = {
     "psm_set_dynamics": ([_P, ctypes.c_int, ctypes.c_double, _D], ctypes.c_int),
     "psm_integrate": ([_P, ctypes.c_double, ctypes.c_int], ctypes.c_int),
     "psm_get_particles": ([_P, ctypes.c_int, _D, _D, _D], ctypes.c_int),
+    "psm_run": ([_P, ctypes.c_int, ctypes.c_double, ctypes.c_int], ctypes.c_int),
     "psm_stream_copy": ([_P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "psm_last_error": ([], ctypes.c_char_p),
 }
@@ -206,6 +207,10 @@ def psm_set_dynamics(ctx, box, density_ratio, accel=None):
 
 def psm_integrate(ctx, dt, scheme):
     return _check(lib().psm_integrate(ctx, float(dt), int(scheme)))
+
+
+def psm_run(ctx, nsteps, dt, scheme):
+    return _check(lib().psm_run(ctx, int(nsteps), float(dt), int(scheme)))
 
 
 def psm_get_particles(ctx, box, n):
@@ -377,6 +382,9 @@ class Engine:
 
     def integrate(self, dt=1.0, scheme=PSM_VERLET):
         psm_integrate(self.ctx, dt, scheme)
+
+    def run(self, nsteps, dt=1.0, scheme=PSM_VERLET):
+        psm_run(self.ctx, nsteps, dt, scheme)
 
     def get_particles(self, box=0):
         return psm_get_particles(self.ctx, box, self.np[box])

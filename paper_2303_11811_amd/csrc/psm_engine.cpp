@@ -230,6 +230,11 @@ struct psm_ctx {
     // graphs of 10 steps, one per starting parity
     bool use_graph = false;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // graphs of 10 (step + sphere update) pairs, per starting parity, for the
+    // time step and scheme they were captured with
+    hipGraphExec_t gexec_dyn[2] = {nullptr, nullptr};
+    double gdyn_dt[2] = {0.0, 0.0};
+    int gdyn_scheme[2] = {-1, -1};
     // kernel timing
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -241,11 +246,16 @@ struct psm_ctx {
 static const int kGraphSteps = 10;
 
 static void drop_graphs(psm_ctx* c) {
-    for (int p = 0; p < 2; ++p)
+    for (int p = 0; p < 2; ++p) {
         if (c->gexec[p]) {
             (void)hipGraphExecDestroy(c->gexec[p]);
             c->gexec[p] = nullptr;
         }
+        if (c->gexec_dyn[p]) {
+            (void)hipGraphExecDestroy(c->gexec_dyn[p]);
+            c->gexec_dyn[p] = nullptr;
+        }
+    }
 }
 
 static int upload_box_table(psm_ctx* c) {
@@ -830,11 +840,9 @@ extern "C" int psm_set_dynamics(psm_ctx* c, int box, double density_ratio, const
     return upload_box_table(c);
 }
 
-extern "C" int psm_integrate(psm_ctx* c, double dt, int scheme) {
-    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
-    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PSM_EINVAL, "dt must be positive and finite");
-    if (scheme != PSM_EULER && scheme != PSM_VERLET) return fail(PSM_EINVAL, "unknown scheme %d", scheme);
-    if (!c->have_particles_lists) return fail(PSM_ESTATE, "no valid particle set");
+// Sphere update and device-side re-binning (no host state is touched, so
+// that it can be captured).
+static int enqueue_integrate(psm_ctx* c, double dt, int scheme) {
     IntParams ip;
     ip.boxes = c->d_boxes;
     ip.part_box = c->d_partbox;
@@ -842,9 +850,80 @@ extern "C" int psm_integrate(psm_ctx* c, double dt, int scheme) {
     ip.P_total = c->P_total;
     ip.dt = dt;
     HIP_TRY(launch_integrate(scheme == PSM_EULER ? SCHEME_EULER : SCHEME_VERLET, ip, c->stream));
+    return rebuild_lists_async(c);
+}
+
+static int check_dynamics_args(psm_ctx* c, double dt, int scheme) {
+    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(PSM_EINVAL, "dt must be positive and finite");
+    if (scheme != PSM_EULER && scheme != PSM_VERLET) return fail(PSM_EINVAL, "unknown scheme %d", scheme);
+    if (!c->have_particles_lists) return fail(PSM_ESTATE, "no valid particle set");
+    return PSM_OK;
+}
+
+extern "C" int psm_integrate(psm_ctx* c, double dt, int scheme) {
+    int rc = check_dynamics_args(c, dt, scheme);
+    if (rc) return rc;
+    rc = enqueue_integrate(c, dt, scheme);
     // the host copies of positions are stale from here on
     for (auto& v : c->last_xr) v.clear();
-    return rebuild_lists_async(c);
+    c->lists_unchecked = true;
+    return rc;
+}
+
+static int build_dyn_graph(psm_ctx* c, int start_parity, double dt, int scheme) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int saved = c->parity;
+    c->parity = start_parity;
+    int rc = PSM_OK;
+    for (int s = 0; s < kGraphSteps && rc == PSM_OK; ++s) {
+        rc = enqueue_step(c, false);
+        if (rc == PSM_OK) rc = enqueue_integrate(c, dt, scheme);
+    }
+    c->parity = saved;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (rc != PSM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(PSM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    if (c->gexec_dyn[start_parity]) (void)hipGraphExecDestroy(c->gexec_dyn[start_parity]);
+    c->gexec_dyn[start_parity] = nullptr;
+    e = hipGraphInstantiate(&c->gexec_dyn[start_parity], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(PSM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    c->gdyn_dt[start_parity] = dt;
+    c->gdyn_scheme[start_parity] = scheme;
+    return PSM_OK;
+}
+
+extern "C" int psm_run(psm_ctx* c, int nsteps, double dt, int scheme) {
+    int rc = check_dynamics_args(c, dt, scheme);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(PSM_EINVAL, "nsteps < 0");
+    int left = nsteps;
+    if (c->use_graph && !c->timing) {
+        while (left >= kGraphSteps) {
+            int p = c->parity;
+            if (!c->gexec_dyn[p] || c->gdyn_dt[p] != dt || c->gdyn_scheme[p] != scheme) {
+                rc = build_dyn_graph(c, p, dt, scheme);
+                if (rc) return rc;
+            }
+            HIP_TRY(hipGraphLaunch(c->gexec_dyn[p], c->stream));
+            left -= kGraphSteps;   // an even count: the parity is unchanged
+        }
+    }
+    for (; left > 0; --left) {
+        rc = enqueue_step(c, c->timing);
+        if (rc == PSM_OK) rc = enqueue_integrate(c, dt, scheme);
+        if (rc) return rc;
+    }
+    if (nsteps > 0) {
+        for (auto& v : c->last_xr) v.clear();
+        c->lists_unchecked = true;
+    }
+    return PSM_OK;
 }
 
 extern "C" int psm_get_particles(psm_ctx* c, int box, double* x, double* U, double* omega) {

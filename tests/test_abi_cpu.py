@@ -79,6 +79,7 @@ def test_null_context_calls():
     assert L.psm_set_graph(None, 1) == psm.PSM_EINVAL
     assert L.psm_get_forces(None, 0, None, None) == psm.PSM_EINVAL
     assert L.psm_integrate(None, 1.0, psm.PSM_VERLET) == psm.PSM_EINVAL
+    assert L.psm_run(None, 10, 1.0, psm.PSM_VERLET) == psm.PSM_EINVAL
     assert L.psm_set_dynamics(None, 0, 1.0, None) == psm.PSM_EINVAL
     assert L.psm_get_particles(None, 0, None, None, None) == psm.PSM_EINVAL
     assert L.psm_set_launch(None, 64, 4, 1, 0) == psm.PSM_EINVAL

@@ -138,3 +138,32 @@ def test_spheres_bounce_off_walls_like_the_oracle():
     assert_pdfs_close(fg, f, 1e-12)
     assert np.allclose(x, dyn.x, rtol=1e-12, atol=1e-12)
     assert np.allclose(U, dyn.U, rtol=1e-12, atol=1e-15)
+
+
+def test_run_replays_graphs_bitwise():
+    """psm_run with graphs (10 step + update pairs per replay, recaptured for a
+    new time step) equals the eager step/integrate loop bit for bit after
+    every chunk, with synchronising reads between the replays."""
+    spec = inputs.random_small((40, 34, 30), 6, (2.5, 4.0), seed=33, tau=0.7, fext=(1e-5, 0, 0),
+                               vamp=0.08, omamp=0.003)
+    chunks = [(10, 1.0), (13, 1.0), (10, 0.5), (10, 0.5), (10, 1.0)]
+    engines = []
+    for graph in (False, True):
+        eng = make_engine([spec])
+        eng.set_pdfs(0, initial_f(spec))
+        eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+        eng.set_dynamics(0, 1.4, (0.0, -1e-4, 0.0))
+        eng.set_graph(graph)
+        engines.append(eng)
+    for n, dt in chunks:
+        eager, graphed = engines
+        for _ in range(n):
+            eager.step(1)
+            eager.integrate(dt, psm.PSM_VERLET)
+        graphed.run(n, dt, psm.PSM_VERLET)
+        a = (*eager.get_particles(0), *eager.get_forces(0), eager.get_pdfs(0).cpu().numpy())
+        b = (*graphed.get_particles(0), *graphed.get_forces(0), graphed.get_pdfs(0).cpu().numpy())
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v), (n, dt)
+    for eng in engines:
+        eng.close()

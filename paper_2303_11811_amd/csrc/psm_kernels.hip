@@ -268,6 +268,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
         }
         const PSM_CONST BoxDev& bx = boxes[b];
         const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
+        // MAP = 1 instantiates the sampling path for contexts in which any box
+        // samples; each box still uses its own mapping
+        const bool lin_map = MAP == 0 || bx.mapping == 0;
         const int ntx = bx.ntx, nty = bx.nty;
         const int lt = t - bx.tile_base;
         const int tcx = lt % ntx;
@@ -340,7 +343,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
                 ey = ey > 0.0 ? ey : 0.0;
                 xy2 = (float)(ex * ex + ey * ey);
                 pz = (float)s_pz[lane];
-                const double lim = s_pr[lane] + (MAP == 0 ? s_pfr[lane] : bx.reach) + 0.05;
+                const double lim = s_pr[lane] + (lin_map ? s_pfr[lane] : bx.reach) + 0.05;
                 lim2 = (float)(lim * lim);
             }
             const float fnz = (float)nz;
@@ -375,7 +378,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
         double dx = min_image(cxc - s_px[c], Lx, hLx);                                                      \
         double dy = min_image(cyc - s_py[c], Ly, hLy);                                                      \
         double dz = min_image(czc - s_pz[c], Lz, hLz);                                                      \
-        double B = MAP == 0 ? overlap_linear(dx, dy, dz, s_pr[c], s_pfr[c])                                 \
+        double B = lin_map ? overlap_linear(dx, dy, dz, s_pr[c], s_pfr[c])                                  \
                             : overlap_subsample(dx, dy, dz, s_pr[c], bx.nsub, bx.sub_off, bx.reach);         \
         if (B > 0.0) slots_insert(sl, c, s_pid[c], B);                                                      \
     } while (0)

@@ -275,3 +275,48 @@ def test_side_walls_roundtrip_and_duct_profile():
     exact = g / (2 * nu) * (x + 0.5) * (H - 0.5 - x) + 2 * g / (3 * nu) * ((tau - 0.5) ** 2 - 3.0 / 16.0)
     prof = u[2].reshape(4, 4, H)[0, 0, :]
     assert np.max(np.abs(prof - exact)) / exact.max() < 1e-9
+
+
+def test_mixed_boxes_in_one_launch():
+    """A periodic box, a channel with moving walls and a closed bed with
+    sub-sampled spheres in one context (one launch per step) each match the
+    oracle run alone, also under device-side sphere updates with different
+    dynamics per box."""
+    specs = [inputs.random_small((30, 28, 26), 4, (2.5, 4.0), seed=51, tau=0.66, fext=(1e-5, 0, 0),
+                                 vamp=0.05, omamp=0.002),
+             _channel((34, 24, 22), 3, seed=52),
+             _bed((26, 30, 28), 3, seed=53, rho_out=1.002)]
+    specs[2].mapping = psm.PSM_MAP_SUBSAMPLE
+    dyn_par = [(1.2, (0.0, 0.0, 0.0)), (1.8, (0.0, 0.0, -2e-4)), (2.5, (1e-4, 0.0, -1e-4))]
+    steps = 8
+    print("[case] mixed boxes", flush=True)
+    refs = []
+    for s, (rho_p, acc) in zip(specs, dyn_par):
+        box = oracle_box_of(s)
+        f = initial_f(s)
+        dyn = oracle.Dynamics(s.x, s.r, s.U, s.Om)
+        for _ in range(steps):
+            ref = oracle.run(box, f, 1, dyn.x, dyn.r, dyn.U, dyn.Om)
+            f = ref.f
+            oracle.integrate(box, dyn, ref.F, ref.T, dt=1.0, scheme=psm.PSM_VERLET, rho_p=rho_p, accel=acc)
+        refs.append((f, ref, dyn))
+    eng = make_engine(specs)
+    eng.set_launch(32, 8, 4, psm.PSM_LAUNCH_FILTER)
+    for b, (s, (rho_p, acc)) in enumerate(zip(specs, dyn_par)):
+        eng.set_pdfs(b, initial_f(s))
+        eng.set_particles(b, s.x, s.r, s.U, s.Om)
+        eng.set_dynamics(b, rho_p, acc)
+    eng.run(steps, 1.0, psm.PSM_VERLET)
+    for b, (f, ref, dyn) in enumerate(refs):
+        assert_pdfs_close(eng.get_pdfs(b).cpu().numpy(), f, 1e-12)
+        F, T = eng.get_forces(b)
+        assert_forces_close(F, ref.F, ref.A)
+        x, U, _ = eng.get_particles(b)
+        assert np.allclose(x, dyn.x, rtol=1e-12, atol=1e-12)
+        assert np.allclose(U, dyn.U, rtol=1e-12, atol=1e-15)
+    eng.close()
+
+
+def oracle_box_of(spec):
+    from psm_cases import oracle_box
+    return oracle_box(spec)

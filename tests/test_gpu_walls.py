@@ -320,3 +320,42 @@ def test_mixed_boxes_in_one_launch():
 def oracle_box_of(spec):
     from psm_cases import oracle_box
     return oracle_box(spec)
+
+
+@pytest.mark.parametrize("storage,tol_u", [(psm.PSM_FP32DEV, 2e-5), (psm.PSM_FP16DEV, 3e-3)])
+def test_mixed_boxes_deviation_forms_with_graphs(storage, tol_u):
+    """Mixed boxes (periodic, wall channel, closed bed with sampled spheres)
+    in a deviation form, persistent grid with the filter, graph replays; then
+    fewer spheres in one box and no spheres in another, and more steps: each
+    box stays within the form's velocity bound of the oracle."""
+    specs = [inputs.random_small((28, 26, 24), 4, (2.5, 4.0), seed=61, tau=0.7, fext=(1e-5, 0, 0)),
+             _channel((30, 22, 20), 3, seed=62),
+             _bed((24, 26, 26), 3, seed=63)]
+    specs[2].mapping = psm.PSM_MAP_SUBSAMPLE
+    print(f"[case] mixed boxes storage={storage}", flush=True)
+    eng = make_engine(specs, storage=storage)
+    eng.set_launch(64, 4, 4, psm.PSM_LAUNCH_PERSISTENT | psm.PSM_LAUNCH_FILTER)
+    eng.set_graph(True)
+    for b, s in enumerate(specs):
+        eng.set_pdfs(b, initial_f(s))
+        eng.set_particles(b, s.x, s.r, s.U, s.Om)
+    eng.step(20)
+    # second phase: box 0 keeps two spheres, box 1 none
+    s0, s1 = specs[0], specs[1]
+    eng.set_particles(0, s0.x[:2], s0.r[:2], s0.U[:2], s0.Om[:2])
+    eng.set_particles(1, np.zeros((0, 3)), np.zeros(0), np.zeros((0, 3)))
+    eng.step(10)
+    got = [eng.get_pdfs(b).cpu().numpy() for b in range(3)]
+    eng.close()
+    phase2 = [dict(x=s0.x[:2], r=s0.r[:2], U=s0.U[:2], Om=s0.Om[:2]),
+              dict(x=np.zeros((0, 3)), r=np.zeros(0), U=np.zeros((0, 3)), Om=np.zeros((0, 3))),
+              dict(x=specs[2].x, r=specs[2].r, U=specs[2].U, Om=specs[2].Om)]
+    for b, s in enumerate(specs):
+        box = oracle_box_of(s)
+        f = oracle.run(box, initial_f(s), 20, s.x, s.r, s.U, s.Om).f
+        p2 = phase2[b]
+        f = oracle.run(box, f, 10, p2["x"], p2["r"], p2["U"], p2["Om"]).f
+        ob = oracle.Box(*s.dims, tau=s.tau)
+        _, u_ref = oracle.macroscopic(ob, f)
+        _, u = oracle.macroscopic(ob, got[b])
+        assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < tol_u, b

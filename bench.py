@@ -426,7 +426,7 @@ def main():
             "cells": spec.N, "spheres": int(len(spec.r)), "storage": "f64",
             "launch": main_res["launch"],
             "step": "kernel only" if args.kernel_only else
-                    "upload spheres + bin + fused map/stream-collide/force + reduce + read forces",
+                    "upload spheres (lists rebuilt only when positions change) + fused map/stream-collide/force + reduce + read forces",
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",

@@ -91,3 +91,40 @@ def test_stream_copy_argument_checks():
     assert L.psm_stream_copy(None, None, 16, None) == psm.PSM_EINVAL
     assert L.psm_stream_copy(ctypes.c_void_p(256), ctypes.c_void_p(4096), 15, None) == psm.PSM_EINVAL
     assert L.psm_stream_copy(ctypes.c_void_p(256), ctypes.c_void_p(264), 64, None) == psm.PSM_EINVAL
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/psm.h compiles as C99 on its own, and a C program calling the
+    host-only entry points links against libpsm.so and runs without a GPU."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "abi.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include "psm.h"
+int main(void) {
+    psm_box_desc d = {0};
+    size_t bytes = 0;
+    d.nx = 40; d.ny = 36; d.nz = 30; d.tau = 0.7;
+    d.max_particles = 4; d.max_radius = 4.0; d.mapping = PSM_MAP_LINEAR; d.subsample_n = 4;
+    d.walls_z = 1; d.face_type[0] = PSM_FACE_VELOCITY; d.face_type[1] = PSM_FACE_PRESSURE;
+    d.face_rho[1] = 1.0;
+    if (psm_workspace_size(&d, 1, PSM_FP32DEV, &bytes) != PSM_OK || bytes == 0) return 1;
+    d.tau = 0.4;
+    if (psm_workspace_size(&d, 1, PSM_FP32DEV, &bytes) != PSM_EINVAL) return 2;
+    if (psm_step(NULL, 1) != PSM_EINVAL) return 3;
+    printf("%zu %s\n", bytes, psm_last_error());
+    return 0;
+}
+''')
+    exe = tmp_path / "abi"
+    libdir = os.path.dirname(psm.LIB_PATH)
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe), "-L", libdir, "-lpsm", f"-Wl,-rpath,{libdir}"], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0, (out.returncode, out.stdout, out.stderr)
+    assert "ctx" in out.stdout

@@ -33,6 +33,12 @@ STORAGE_NAME = {0: "f64", 1: "f32dev", 2: "f16dev"}
 COUNTER_FILE = os.path.join(ROOT, "profiles", "k_psm_step_f64_512_counters.json")
 
 
+def lightspeed_ms(cells, storage, gbps):
+    """Roofline time of one step (Sec. 4.2.1, eq. 28): the algorithmic PDF
+    bytes of `cells` cells in the given storage form at `gbps` GB/s."""
+    return cells * BYTES_PER_CELL[storage] / (gbps * 1e9) * 1e3
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -290,11 +296,38 @@ def run_fluidized_bed(psm, torch, inputs, case, steps=200, warmup=5):
     eng.close()
     torch.cuda.empty_cache()
     kern = kms / max(nl, 1)
+    # the paper's comparison (Sec. 4.2.1): the same kernel, launch and
+    # boundaries with no spheres in the box
+    kern0 = bed_kernel_without_spheres(psm, torch, spec, shape)
     return {"case": case, "cells": spec.N, "spheres": int(len(spec.r)), "steps": steps, "storage": "f64",
             "mlups": spec.N * steps / dt / 1e6, "ms_per_step": dt * 1e3 / steps, "kernel_ms": kern,
             "roofline_frac": spec.N * BYTES_PER_CELL[0] / (kern * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+            "kernel_ms_no_spheres": kern0, "kernel_over_no_spheres": kern / kern0 - 1.0,
             "launch": list(shape), "slot_overflows_last_map": ov, "forces_finite": bool(np.all(np.isfinite(F))),
             "particle_update": "device velocity Verlet (psm_run: graphs of 10 step + update pairs)"}
+
+
+def bed_kernel_without_spheres(psm, torch, spec, shape, steps=30):
+    """Average step-kernel time of the bed box with the spheres removed."""
+    import numpy as np
+
+    eng = psm.Engine([psm.desc_from_spec(spec, max_radius=10.0)], storage=psm.PSM_FP64)
+    with torch.cuda.stream(eng.stream):
+        u0 = torch.as_tensor(spec.u0, dtype=torch.float64).to(eng.device)
+    eng.set_particles(0, np.zeros((0, 3)), np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)))
+    eng.set_launch(*shape)
+    eng.set_equilibrium(0, u0)
+    del u0
+    eng.step(5)
+    eng.synchronize()
+    eng.reset_timing()
+    eng.set_timing(True)
+    eng.step(steps)
+    eng.synchronize()
+    nl, kms = eng.get_timing()
+    eng.close()
+    torch.cuda.empty_cache()
+    return kms / max(nl, 1)
 
 
 def cpu_baseline(inputs, n, steps):
@@ -403,6 +436,14 @@ def main():
         log("cpu baseline (oracle)")
         cpu = cpu_baseline(inputs, args.cpu_size, args.cpu_steps)
         log(f"  {cpu}")
+
+    for case in ("dilute", "dense"):
+        bed = extra.get(f"fluidized_bed_{case}")
+        if bed is not None:
+            # the paper's lightspeed (eq. 28) with this box's measured copy rate
+            t_min = lightspeed_ms(bed["cells"], 0, copy_gbps)
+            bed["lightspeed_ms_at_copy_rate"] = t_min
+            bed["kernel_over_lightspeed"] = bed["kernel_ms"] / t_min - 1.0
 
     algo_bytes = spec.N * BYTES_PER_CELL[0]
     achieved = algo_bytes / (main_res["kernel_ms"] * 1e-3) / 1e9

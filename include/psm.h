@@ -220,10 +220,12 @@ int psm_set_launch(psm_ctx* ctx, int tx, int ty, int tz, int flags);
 int psm_get_launch(psm_ctx* ctx, int* tx, int* ty, int* tz, int* flags);
 
 /* Time every allowed launch shape and flag combination on this context with
- * HIP events (warmup + trial_steps steps each), keep the fastest and report
- * it (host outputs, each may be NULL). The trial steps advance and overwrite
- * the PDF state: set the state after tuning. Synchronises. best_ms: ms per
- * step of the chosen launch. */
+ * HIP events (2 untimed + trial_steps timed steps each), then time the four
+ * fastest twice more, interleaved, with 2 * trial_steps steps each; keep the
+ * one with the smallest mean of those two and report it (host outputs, each
+ * may be NULL). The trial steps advance and overwrite the PDF state: set the
+ * state after tuning. Synchronises. best_ms: ms per step of the chosen launch
+ * in the second round. */
 int psm_autotune(psm_ctx* ctx, int trial_steps, int* tx, int* ty, int* tz, int* flags, double* best_ms);
 
 /* Enable (1) / disable (0) HIP-graph replay of 10-step sequences in psm_step. */

@@ -28,8 +28,10 @@ struct BoxDev {
     int nx, ny, nz, N;
     int ntx, nty, ntz, tile_base;   // tiles per axis, first global tile
     int part_base, np, mapping, nsub;
-    // PDF storage: each z-plane holds pblk blocks of 64 cells (nx*ny rounded
-    // up); a block stores its 19 directions one after another, 64 values each.
+    // PDF storage: each z-plane holds pblk blocks of 64 cells (pitch*ny
+    // rounded up); a block stores its 19 directions one after another, 64
+    // values each. Cell (x, y) of a plane is in-plane cell x + pitch*y.
+    int pitch;                      // row pitch in cells, see row_pitch()
     int pblk;                       // blocks per z-plane
     long long plane_elems;          // values per z-plane, pblk * 19 * 64
     void* grid[2];                  // ping-pong PDF grids, nz * plane_elems values
@@ -120,9 +122,19 @@ __host__ __device__ inline void aabb_cells(double x, double r, int& lo, int& hi)
     hi = (int)floor(x + (r + 1.0));
 }
 
+// Row pitch of the PDF layout: a row that does not fill whole 64-cell
+// blocks is padded to the next block boundary when that costs at most 1/8 of
+// the row, so that every row of a tile starts on a block and a wave's loads
+// and stores of one direction stay in one block (or two, for a shift in x).
+// Narrower rows are packed back to back.
+__host__ __device__ inline int row_pitch(int nx) {
+    int up = (nx + BLK - 1) / BLK * BLK;
+    return 8LL * up <= 9LL * nx ? up : nx;
+}
+
 // Element index of direction q of cell (x, y, z) in a box's PDF grid.
 __host__ __device__ inline long long pdf_index(const BoxDev& b, int q, int x, int y, int z) {
-    int s = x + b.nx * y;
+    int s = x + b.pitch * y;
     return (long long)z * b.plane_elems + (long long)(s / BLK) * (NQ * BLK) + q * BLK + (s % BLK);
 }
 

@@ -300,9 +300,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
         const int ym = ys == 0 ? ny - 1 : ys - 1, yp = ys == ny - 1 ? 0 : ys + 1;
         // byte offsets inside a z-plane of the nine (x, y) source columns;
         // they do not depend on z
-        const int nxl = nx;
-        auto inplane = [nxl](int xx, int yy) -> unsigned {
-            int c = xx + nxl * yy;
+        const int pitch = bx.pitch;
+        auto inplane = [pitch](int xx, int yy) -> unsigned {
+            int c = xx + pitch * yy;
             return (unsigned)(((c / BLK) * (NQ * BLK) + (c % BLK)) * (int)sizeof(T));
         };
         // lanes next to a resting side wall (x = 0, nx - 1; y = 0, ny - 1): bits 0-3

@@ -52,6 +52,10 @@ RAGGED = [
     ((70, 21, 18), (16, 16, 2, 2), 3, True),
     ((33, 40, 27), (128, 2, 8, 3), 6, True),
     ((24, 24, 24), (256, 1, 32, 2), 2, False),
+    # row pitch padded to whole 64-cell blocks (nx 60 -> 64, nx 121 -> 128)
+    ((60, 22, 18), (64, 4, 4), 4, True),
+    ((121, 14, 12), (128, 2, 8, 3), 5, False),
+    ((60, 22, 18), (32, 8, 2, 2), 4, True),
 ]
 
 
@@ -239,3 +243,24 @@ def test_candidate_filter_is_exact(storage):
             out.append((f, F, T, B, pid))
         for a, b in zip(*out):
             assert np.array_equal(a, b)
+
+
+def test_autotune_picks_an_allowed_launch_and_keeps_parity():
+    """The tuner's pick is one of the documented shapes, is the launch the
+    context keeps, and the step under it still matches the oracle."""
+    spec = inputs.random_small((60, 22, 18), 4, (2.5, 4.0), seed=81, tau=0.7, fext=(1e-5, 0, 0), overlap=True)
+    print("[case] autotune", flush=True)
+    eng = make_engine([spec])
+    eng.set_pdfs(0, initial_f(spec))
+    eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+    shape, ms = eng.autotune(trial_steps=2)
+    tx, ty, tz, flags = shape
+    assert tx in (16, 32, 64, 128, 256) and tx * ty == 256 and tz in (1, 2, 4, 8, 16, 32)
+    assert flags in (0, 1, 2, 3) and ms > 0.0
+    assert tuple(eng.get_launch()) == tuple(shape)
+    ref = run_oracle(spec, 10)
+    f, F, T, B, pid, eng = run_engine(spec, 10, eng=eng)
+    assert_pdfs_close(f, ref.f, 1e-12)
+    assert np.array_equal(pid, ref.pid)
+    assert_forces_close(F, ref.F, ref.A)
+    eng.close()

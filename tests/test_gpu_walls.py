@@ -225,7 +225,9 @@ def _bed(dims, n, seed, tau=0.7, U=(0.0, 0.0, 0.01), rho_out=1.0):
 
 
 @pytest.mark.parametrize("dims,launch", [((30, 22, 26), (32, 8, 4, 0)), ((41, 27, 19), (64, 4, 8, 3)),
-                                         ((20, 36, 24), (16, 16, 2, 2))])
+                                         ((20, 36, 24), (16, 16, 2, 2)),
+                                         # rows padded to a 64-cell block (pitch 64 for nx 59)
+                                         ((59, 18, 22), (64, 4, 4, 2))])
 def test_side_walls_bed_parity_fp64(dims, launch):
     spec = _bed(dims, 4, seed=sum(dims), rho_out=1.001)
     print(f"[case] bed fp64 dims={dims} launch={launch}", flush=True)

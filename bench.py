@@ -355,7 +355,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-size", type=int, default=128)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--batched-steps", type=int, default=500)
     ap.add_argument("--dense-steps", type=int, default=200)
     ap.add_argument("--dense-size", type=int, default=768)

@@ -97,31 +97,57 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// Wave sums of six values at once (a butterfly that splits the values
-// between the exchanging lanes: 10 exchanges instead of 36). On return every
-// lane holds the total of value (4 b5 + 2 b4 + b3), b_k the bits of its lane
-// index; values 6 and 7 are zero padding. The order of the additions is
-// fixed, so the result is reproducible bit for bit.
+// Cross-lane moves of a double. DPP forms stay inside a row of 16 lanes and
+// run on the vector ALU: quad permutations, the mirror inside each half row
+// (lane i <-> 7 - i of its group of 8) and the rotation of a row by 8 (lane
+// i <-> i ^ 8). Lane i ^ 16 comes from a swizzle inside 32 lanes, lane i ^ 32
+// from a permute.
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+constexpr int DPP_QUAD_XOR1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_ROW_ROR8 = 0x128;
+__device__ __forceinline__ double swizzle_xor16(double v) {
+    // bit mode: and mask 0x1f, or mask 0, xor mask 0x10
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_swizzle((int)b, 0x401F);
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Wave sums of six values at once. Inside each group of 8 lanes a butterfly
+// splits the values (padded to 8) between exchanging lanes: the mirror pair
+// by bit 2 of the lane, then quad partners by bits 1 and 0 (7 exchanges),
+// after which lane l holds the group's sum of value l & 7; three exchanges
+// across groups finish the sums. All within-group moves are DPP. Every lane
+// returns the total of value `comp` = l & 7 (values 6 and 7 are padding).
+// The order of the additions is fixed, so the result is reproducible bit for
+// bit, and partners add the same two numbers, so all lanes of one value agree.
 __device__ inline double wave_sum6(const double v[6], int lane, int& comp) {
-    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+    const bool b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
     double a[4], b[2];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const double lo = v[i], hi = i + 4 < 6 ? v[i + 4] : 0.0;
-        const double keep = b5 ? hi : lo, send = b5 ? lo : hi;
-        a[i] = keep + __shfl_xor(send, 32, 64);
+        const double keep = b2 ? hi : lo, send = b2 ? lo : hi;
+        a[i] = keep + dpp_f64<DPP_ROW_HALF_MIRROR>(send);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        const double keep = b4 ? a[i + 2] : a[i], send = b4 ? a[i] : a[i + 2];
-        b[i] = keep + __shfl_xor(send, 16, 64);
+        const double keep = b1 ? a[i + 2] : a[i], send = b1 ? a[i] : a[i + 2];
+        b[i] = keep + dpp_f64<DPP_QUAD_XOR2>(send);
     }
-    const double keep = b3 ? b[1] : b[0], send = b3 ? b[0] : b[1];
-    double d = keep + __shfl_xor(send, 8, 64);
-    d += __shfl_xor(d, 4, 64);
-    d += __shfl_xor(d, 2, 64);
-    d += __shfl_xor(d, 1, 64);
-    comp = (b5 ? 4 : 0) + (b4 ? 2 : 0) + (b3 ? 1 : 0);
+    const double keep = b0 ? b[1] : b[0], send = b0 ? b[0] : b[1];
+    double d = keep + dpp_f64<DPP_QUAD_XOR1>(send);
+    d += dpp_f64<DPP_ROW_ROR8>(d);
+    d += swizzle_xor16(d);
+    d += __shfl_xor(d, 32, 64);
+    comp = lane & 7;
     return d;
 }
 
@@ -555,7 +581,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
                     if (live == 0ull) break;
                     int leader = __ffsll((long long)live) - 1;
                     int mine = pend0 >= 0 ? pend0 : pend1;
-                    int c = __shfl(mine, leader, 64);
+                    // the leader's candidate, read into a scalar register
+                    const int c = __builtin_amdgcn_readlane(mine, leader);
                     double Bs = 0.0;
                     if (pend0 == c) { Bs = B0; pend0 = -1; }
                     else if (pend1 == c) { Bs = B1; pend1 = -1; }
@@ -575,7 +602,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
                     }
                     int comp;
                     const double sum = wave_sum6(v, lane, comp);
-                    if ((lane & 7) == 0 && comp < 6) s_acc[wave][comp][c] += sum;
+                    if (lane < 6) s_acc[wave][comp][c] += sum;
                 }
             }
         }

@@ -249,12 +249,14 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
         dt = time.perf_counter() - t0
         nl, kms = eng.get_timing()
     _, _, ov = eng.get_stats(0)
+    kern0 = kernel_ms_without_spheres(eng) if device else None
     eng.close()
     torch.cuda.empty_cache()
     step_ms = dt * 1e3 / steps
     kern = kms / max(nl, 1)
+    extra = {} if kern0 is None else {"kernel_ms_no_spheres": kern0, "kernel_over_no_spheres": kern / kern0 - 1.0}
     return {"cells": spec.N, "spheres": int(len(spec.r)), "steps": steps, "storage": "f32dev",
-            "mlups": spec.N * steps / dt / 1e6, "ms_per_step": step_ms, "kernel_ms": kern,
+            "mlups": spec.N * steps / dt / 1e6, "ms_per_step": step_ms, "kernel_ms": kern, **extra,
             "coupling_overhead_frac": (step_ms - kern) / step_ms, "launch": list(shape),
             "slot_overflows_last_map": ov,
             "particle_update": "device explicit Euler (psm_run: graphs of 10 step + update pairs)" if device

@@ -128,3 +128,17 @@ int main(void) {
     out = subprocess.run([str(exe)], capture_output=True, text=True)
     assert out.returncode == 0, (out.returncode, out.stdout, out.stderr)
     assert "ctx" in out.stdout
+
+
+def test_row_pitch_padding_in_workspace_size():
+    """Rows are padded to whole 64-cell blocks when that adds at most 1/8 to
+    the row (nx 57-64 take the grid bytes of nx 64), narrower ones are packed
+    (nx 56 takes less). Tile counts agree for these widths at every tile
+    width, so the grids are the only difference."""
+    def ws(nx):
+        return psm.psm_workspace_size([psm.make_desc(nx, 16, 8, 0.6, max_particles=2, max_radius=2.0)],
+                                      psm.PSM_FP64)
+    assert ws(60) == ws(64) and ws(57) == ws(64)
+    grid64 = 2 * 8 * (64 * 16 // 64) * 19 * 64 * 8
+    grid56 = 2 * 8 * -(-(56 * 16) // 64) * 19 * 64 * 8
+    assert ws(64) - ws(56) == grid64 - grid56

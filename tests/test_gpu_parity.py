@@ -264,3 +264,52 @@ def test_autotune_picks_an_allowed_launch_and_keeps_parity():
     assert np.array_equal(pid, ref.pid)
     assert_forces_close(F, ref.F, ref.A)
     eng.close()
+
+
+def test_state_and_argument_errors_on_a_live_context():
+    """The documented codes on a live context, each leaving it usable: more
+    spheres than max_particles (PSM_ECAPACITY), radius out of range, box out
+    of range, NULL buffers, bad time step, scheme, density ratio, launch or
+    trial count (PSM_EINVAL); a context with no spheres set steps as plain
+    LBM; forces read before any step of a sphere set are zeros; afterwards
+    the context still matches the oracle."""
+    import ctypes
+
+    spec = inputs.random_small((30, 20, 16), 3, (2.5, 3.5), seed=97, tau=0.75, fext=(1e-5, 0, 0), vamp=0.01)
+    print("[case] state and argument errors", flush=True)
+    eng = make_engine([spec], max_particles=3, max_radius=4.0)
+    L = psm.lib()
+    assert L.psm_step(eng.ctx, 1) == psm.PSM_OK
+    x4 = np.vstack([spec.x, spec.x[:1]])
+    with pytest.raises(psm.PsmError) as e:
+        eng.set_particles(0, x4, np.full(4, 3.0), np.zeros((4, 3)))
+    assert e.value.code == psm.PSM_ECAPACITY
+    for bad_r in (0.5, 4.5):
+        with pytest.raises(psm.PsmError) as e:
+            eng.set_particles(0, spec.x, np.array([3.0, bad_r, 3.0]), spec.U)
+        assert e.value.code == psm.PSM_EINVAL and "radius" in str(e.value)
+    with pytest.raises(psm.PsmError) as e:
+        eng.set_particles(1, spec.x, spec.r, spec.U)
+    assert e.value.code == psm.PSM_EINVAL and "out of range" in str(e.value)
+    eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+    F, T = eng.get_forces(0)
+    assert not F.any() and not T.any()
+    assert L.psm_get_pdfs(eng.ctx, 0, None) == psm.PSM_EINVAL
+    assert L.psm_get_forces(eng.ctx, 0, None, None) == psm.PSM_EINVAL
+    assert L.psm_integrate(eng.ctx, 0.0, psm.PSM_EULER) == psm.PSM_EINVAL
+    assert L.psm_integrate(eng.ctx, 1.0, 7) == psm.PSM_EINVAL
+    assert L.psm_run(eng.ctx, -1, 1.0, psm.PSM_EULER) == psm.PSM_EINVAL
+    assert L.psm_set_dynamics(eng.ctx, 0, 0.0, None) == psm.PSM_EINVAL
+    assert L.psm_set_dynamics(eng.ctx, 0, float("nan"), None) == psm.PSM_EINVAL
+    acc = (ctypes.c_double * 3)(0.0, float("inf"), 0.0)
+    assert L.psm_set_dynamics(eng.ctx, 0, 2.0, acc) == psm.PSM_EINVAL
+    assert L.psm_set_launch(eng.ctx, 64, 8, 4, 0) == psm.PSM_EINVAL
+    assert L.psm_set_launch(eng.ctx, 64, 4, 3, 0) == psm.PSM_EINVAL
+    assert L.psm_set_launch(eng.ctx, 64, 4, 4, 8) == psm.PSM_EINVAL
+    assert L.psm_autotune(eng.ctx, 0, None, None, None, None, None) == psm.PSM_EINVAL
+    # still usable, and still right
+    ref = run_oracle(spec, 8)
+    f, F, T, B, pid, eng = run_engine(spec, 8, eng=eng)
+    assert_pdfs_close(f, ref.f, 1e-12)
+    assert_forces_close(F, ref.F, ref.A)
+    eng.close()

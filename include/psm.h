@@ -240,7 +240,7 @@ int psm_get_timing(psm_ctx* ctx, long long* launches, double* total_ms);
 int psm_reset_timing(psm_ctx* ctx);
 
 /* Bandwidth reference (the paper's SCALE/STREAM measurement, Sec. 4): copy
- * `bytes` (multiple of 16, at most 2^31 * 8 KiB) from src to dst (device,
+ * `bytes` (multiple of 16, at most 2^31 * 4 KiB) from src to dst (device,
  * 16-byte aligned, not overlapping) on hip_stream with a plain one-shot
  * streaming copy kernel. */
 int psm_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream);

@@ -60,10 +60,10 @@ RAGGED = [
 
 
 @pytest.mark.parametrize("dims,tiles,npart,overlap", RAGGED)
-def test_parity_ragged_linear(dims, tiles, npart, overlap):
+def test_parity_ragged_linear(dims, tiles, npart, overlap, radii=(2.5, 4.0)):
     """Boxes that are not multiples of the tile, several tiles per axis,
     body force, rotating spheres, overlapping spheres (renormalised slots)."""
-    spec = inputs.random_small(dims, npart, (2.5, 4.0), seed=sum(dims), tau=0.67,
+    spec = inputs.random_small(dims, npart, radii, seed=sum(dims), tau=0.67,
                                fext=(2e-5, -1e-5, 5e-6), vamp=0.01, omamp=0.002, overlap=overlap)
     _print_case("ragged", dims=dims, tiles=tiles, n=len(spec.r))
     steps = 12
@@ -77,6 +77,19 @@ def test_parity_ragged_linear(dims, tiles, npart, overlap):
     _, _, ov = eng.get_stats(0)
     # overflow count of the current mapping equals the oracle's
     assert ov == ref.overflow
+
+
+@pytest.mark.parametrize("dims,tiles,npart,radii", [
+    # the smallest spheres allowed (r = 1: f(r) needs r^2 > 1/2), many per tile
+    ((24, 20, 16), (64, 4, 4, 0), 12, (1.0, 1.5)),
+    ((24, 20, 16), (16, 16, 2, 3), 12, (1.0, 1.5)),
+    # one sphere nearly as large as the box allows (L >= 2 (r + 1) + 2): its
+    # bounding box wraps in every axis and covers most tiles
+    ((24, 24, 22), (32, 8, 4, 2), 1, (9.0, 9.0)),
+])
+def test_parity_extreme_radii(dims, tiles, npart, radii):
+    """The radius limits of the linear mapping, checked like the ragged cases."""
+    test_parity_ragged_linear(dims, tiles, npart, npart > 1, radii=radii)
 
 
 def test_parity_no_particles_with_force():

@@ -30,7 +30,12 @@ HBM_PEAK_GBPS = 8000.0
 METRIC = "PSM-LBM MLUPS & % HBM roofline, FP64 vs FP32/FP16-storage at stated error"
 BYTES_PER_CELL = {0: 304, 1: 152, 2: 76}
 STORAGE_NAME = {0: "f64", 1: "f32dev", 2: "f16dev"}
-COUNTER_FILE = os.path.join(ROOT, "profiles", "k_psm_step_f64_512_counters.json")
+STORAGE_OF = {v: k for k, v in STORAGE_NAME.items()}
+DTYPE = {0: "f64", 1: "f32", 2: "f32"}   # arithmetic of the step in each storage form
+
+
+def counter_file(storage):
+    return os.path.join(ROOT, "profiles", f"k_psm_step_{STORAGE_NAME[storage]}_512_counters.json")
 
 
 def lightspeed_ms(cells, storage, gbps):
@@ -51,12 +56,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(storage=0):
     """(HBM bytes per launch, launch shape of the counter run) from the
-    committed rocprofv3 counters, if they were taken on the current kernel
-    source; (None, None) otherwise."""
+    committed rocprofv3 counters of the storage form, if they were taken on
+    the current kernel source; (None, None) otherwise."""
     try:
-        with open(COUNTER_FILE) as fh:
+        with open(counter_file(storage)) as fh:
             c = json.load(fh)
     except (OSError, ValueError):
         return None, None
@@ -353,6 +358,8 @@ def main():
     ap.add_argument("--launch", type=str, default=None, help="tx,ty,tz,flags (skips the autotuner)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--kernel-only", action="store_true", help="time psm_step alone (no upload/readback)")
+    ap.add_argument("--storage", choices=list(STORAGE_OF), default="f64",
+                    help="storage form of the main run (another than f64 skips the precision-form runs)")
     ap.add_argument("--precision-steps", type=int, default=200)
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -384,21 +391,24 @@ def main():
     spec = inputs.paper_scale(n=args.size, seed=1)
     log(f"workload: {args.size}^3, {len(spec.r)} spheres, tau {spec.tau}, g {spec.fext[0]}")
 
-    log("FP64 main run")
-    main_res = run_case(psm, torch, spec, 0, args.steps, args.warmup, not args.no_autotune, launch,
+    main_st = STORAGE_OF[args.storage]
+    log(f"{args.storage} main run")
+    main_res = run_case(psm, torch, spec, main_st, args.steps, args.warmup, not args.no_autotune, launch,
                         full_loop=not args.kernel_only)
     log(f"  {main_res}")
 
     forms = {}
-    if not args.no_precision:
+    if not args.no_precision and main_st == 0:
         for st in (1, 2):
             log(f"{STORAGE_NAME[st]} run")
             r = run_case(psm, torch, spec, st, args.precision_steps, 10, not args.no_autotune, None,
                          full_loop=not args.kernel_only)
             r["roofline_frac"] = spec.N * BYTES_PER_CELL[st] / (r["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS
+            traffic, traffic_launch = measured_traffic(st)
             forms[STORAGE_NAME[st]] = {"mlups": r["mlups"], "ms_per_step": r["ms_per_step"],
                                        "kernel_ms": r["kernel_ms"], "launch": r["launch"],
                                        "roofline_frac": r["roofline_frac"],
+                                       "traffic": traffic, "traffic_launch": traffic_launch,
                                        "speedup_vs_f64": r["mlups"] / main_res["mlups"]}
             log(f"  {forms[STORAGE_NAME[st]]}")
         log("precision errors (64^3 copy, 1000 steps, vs the FP64 path)")
@@ -442,9 +452,10 @@ def main():
             bed["lightspeed_ms_at_copy_rate"] = t_min
             bed["kernel_over_lightspeed"] = bed["kernel_ms"] / t_min - 1.0
 
-    algo_bytes = spec.N * BYTES_PER_CELL[0]
+    algo_bytes = spec.N * BYTES_PER_CELL[main_st]
     achieved = algo_bytes / (main_res["kernel_ms"] * 1e-3) / 1e9
-    traffic, traffic_launch = measured_traffic()
+    traffic, traffic_launch = measured_traffic(main_st)
+    form = {0: "FP64", 1: "FP32-deviation storage", 2: "FP16-deviation storage"}[main_st]
     out = {
         "metric": METRIC,
         "value": round(main_res["mlups"], 1),
@@ -456,12 +467,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": DTYPE[main_st],
         "data": "synthetic",
         "config": {
-            "workload": f"PSM-LBM D3Q19 SRT, {args.size}^3 periodic, FP64, tau 0.55, body force 1e-6 +x, "
+            "workload": f"PSM-LBM D3Q19 SRT, {args.size}^3 periodic, {form}, tau 0.55, body force 1e-6 +x, "
                         f"{len(spec.r)} spheres d=20 (10% solid), mapping + force/torque every step",
-            "cells": spec.N, "spheres": int(len(spec.r)), "storage": "f64",
+            "cells": spec.N, "spheres": int(len(spec.r)), "storage": args.storage,
             "launch": main_res["launch"],
             "step": "kernel only" if args.kernel_only else
                     "upload spheres (lists rebuilt only when positions change) + fused map/stream-collide/force + reduce + read forces",
@@ -471,13 +482,13 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
             "traffic_launch": traffic_launch,
-            "kernel": "k_psm_step<f64>", "kernel_ms": round(main_res["kernel_ms"], 4),
+            "kernel": f"k_psm_step<{args.storage}>", "kernel_ms": round(main_res["kernel_ms"], 4),
             "algorithmic_bytes_per_launch": algo_bytes,
             "frac_of_stream_copy": round(achieved / copy_gbps, 4),
         },
         "cpu_baseline": cpu,
         "stream_copy_GBps": round(copy_gbps, 1),
-        "mlups_frac_of_stream_copy": round(main_res["mlups"] * 1e6 * BYTES_PER_CELL[0] / 1e9 / copy_gbps, 4),
+        "mlups_frac_of_stream_copy": round(main_res["mlups"] * 1e6 * BYTES_PER_CELL[main_st] / 1e9 / copy_gbps, 4),
         "precision_forms": forms,
         "other_workloads": extra,
     }

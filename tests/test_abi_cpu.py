@@ -142,3 +142,33 @@ def test_row_pitch_padding_in_workspace_size():
     grid64 = 2 * 8 * (64 * 16 // 64) * 19 * 64 * 8
     grid56 = 2 * 8 * -(-(56 * 16) // 64) * 19 * 64 * 8
     assert ws(64) - ws(56) == grid64 - grid56
+
+
+def test_last_error_is_per_thread():
+    """Two threads failing in different ways each read back their own error
+    text (psm_last_error is thread-local)."""
+    import threading
+
+    L = psm.lib()
+    bad = {"tau": psm.make_desc(8, 8, 8, 0.4), "dimension": psm.make_desc(3, 8, 8, 0.6)}
+    seen = {}
+    barrier = threading.Barrier(2)
+
+    def worker(key):
+        arr = psm._desc_array([bad[key]])
+        out = ctypes.c_size_t(0)
+        msgs = []
+        for _ in range(200):
+            barrier.wait()
+            assert L.psm_workspace_size(arr, 1, psm.PSM_FP64, ctypes.byref(out)) == psm.PSM_EINVAL
+            barrier.wait()
+            msgs.append(psm.psm_last_error())
+        seen[key] = msgs
+
+    ts = [threading.Thread(target=worker, args=(k,)) for k in bad]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    for key, msgs in seen.items():
+        assert len(msgs) == 200 and all(key in m for m in msgs), (key, set(msgs))

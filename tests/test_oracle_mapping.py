@@ -14,7 +14,7 @@ import oracle
 def test_Va_closed_form_matches_quadrature(r):
     # eq. (27): V_a is the integral of sqrt(r^2 - x^2 - y^2) over the unit square
     val, err = integrate.dblquad(lambda y, x: math.sqrt(r * r - x * x - y * y), -0.5, 0.5, -0.5, 0.5,
-                                 epsabs=1e-14, epsrel=1e-14)
+                                 epsabs=2e-13, epsrel=2e-13)
     assert abs(oracle.Va(r) - val) <= 1e-12 * max(1.0, val)
 
 

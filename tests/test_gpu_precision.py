@@ -71,3 +71,35 @@ def test_deviation_storage_roundtrip(storage):
     else:
         ulp = np.abs(d0) * 2.0 ** -10 + 2.0 ** -24 / 1024 + 1e-16
         assert np.all(np.abs(f - f0) <= ulp)
+
+
+@pytest.mark.parametrize("scale", [2.0 ** 8, 2.0 ** 12])
+def test_fp16_scale_choice(scale):
+    """Other power-of-two FP16 scales (the scale is folded into the collision
+    constants) give the same physics within the FP16 bounds, and the state
+    round trip keeps one FP16 rounding of scale * d."""
+    spec = _spec()
+    steps = 100
+    ref = run_oracle(spec, steps)
+    box = oracle.Box(*spec.dims, tau=spec.tau)
+    _, u_ref = oracle.macroscopic(box, ref.f)
+    eng = make_engine([spec], storage=psm.PSM_FP16DEV, fp16_scale=scale)
+    f0 = initial_f(spec)
+    eng.set_pdfs(0, f0)
+    w = oracle.lattice()[1][:, None]
+    back = eng.get_pdfs(0).cpu().numpy()
+    # store: FP64 -> FP32 -> FP16 of scale * d; read: FP32 product with 1/scale, then + w in FP64
+    h = ((f0 - w) * scale).astype(np.float32).astype(np.float16)
+    expect = (h.astype(np.float32) * np.float32(1.0 / scale)).astype(np.float64) + w
+    assert np.array_equal(back, expect)
+    eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+    eng.step(steps)
+    _, u = eng.get_macroscopic(0)
+    F, T = eng.get_forces(0)
+    u = u.cpu().numpy()
+    l2 = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+    fe = np.max(np.linalg.norm(F - ref.F, axis=1) / np.linalg.norm(ref.F, axis=1))
+    print(f"[precision] FP16 scale {scale:g}: L2 u {l2:.3e}, max rel force {fe:.3e}", flush=True)
+    bu, bf = BOUNDS[psm.PSM_FP16DEV]
+    assert l2 <= bu and fe <= bf
+    eng.close()

@@ -141,6 +141,27 @@ def test_graph_replay_equals_eager_bitwise():
     eng.step(7)
     f2 = eng.get_pdfs(0).cpu().numpy()
     assert np.array_equal(f2, f_e)
+    eng.close()
+    # every replay checked against the eager engine, with synchronising reads
+    # and eager steps of the graph engine (odd counts switch the captured
+    # graph's starting parity) between the replays
+    engines = []
+    for graph in (False, True):
+        e = make_engine([spec])
+        e.set_graph(graph)
+        e.set_pdfs(0, initial_f(spec))
+        e.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+        engines.append(e)
+    eager, graphed = engines
+    for n in (10, 10, 3, 10, 10, 1, 20):
+        eager.step(n)
+        graphed.step(n)
+        assert np.array_equal(eager.get_pdfs(0).cpu().numpy(), graphed.get_pdfs(0).cpu().numpy()), n
+        Fa, Ta = eager.get_forces(0)
+        Fb, Tb = graphed.get_forces(0)
+        assert np.array_equal(Fa, Fb) and np.array_equal(Ta, Tb), n
+    for e in engines:
+        e.close()
 
 
 def test_deterministic_repeat():

@@ -207,14 +207,22 @@ __device__ __forceinline__ void pair_psm(R& fq, R& fb, R base, R Ux, R Uy, R Uz,
     fb = nb;
 }
 
-// Particle velocity at the cell centre, eq. (20): U_p + Omega x d.
-__device__ __forceinline__ void particle_velocity(int c, double dx, double dy, double dz, const double* ux,
-                                                  const double* uy, const double* uz, const double* ox,
-                                                  const double* oy, const double* oz, double& vx, double& vy,
-                                                  double& vz) {
-    vx = ux[c] + (oy[c] * dz - oz[c] * dy);
-    vy = uy[c] + (oz[c] * dx - ox[c] * dz);
-    vz = uz[c] + (ox[c] * dy - oy[c] * dx);
+// Lever arm d = x - x_p (minimum image, taken in FP64) and particle velocity
+// at the cell centre (eq. 20) times the storage scale sc, in the collision's
+// precision R: FP64 for FP64 storage, FP32 for the deviation forms.
+template <class R>
+__device__ __forceinline__ void slot_geometry(int c, double cxc, double cyc, double czc, double Lx, double hLx,
+                                              double Ly, double hLy, double Lz, double hLz, const double* px,
+                                              const double* py, const double* pz, const double* ux,
+                                              const double* uy, const double* uz, const double* ox,
+                                              const double* oy, const double* oz, R sc, R& dx, R& dy, R& dz,
+                                              R& Vx, R& Vy, R& Vz) {
+    dx = (R)min_image(cxc - px[c], Lx, hLx);
+    dy = (R)min_image(cyc - py[c], Ly, hLy);
+    dz = (R)min_image(czc - pz[c], Lz, hLz);
+    Vx = sc * ((R)ux[c] + ((R)oy[c] * dz - (R)oz[c] * dy));
+    Vy = sc * ((R)uy[c] + ((R)oz[c] * dx - (R)ox[c] * dz));
+    Vz = sc * ((R)uz[c] + ((R)ox[c] * dy - (R)oy[c] * dx));
 }
 
 // Waves per SIMD the register budget of the step kernel is cut for: 3 for
@@ -528,10 +536,10 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
                     // slot terms with U_p(x) of eq. (20)
                     R Bt = 0, A0 = 0, Mxx = 0, Myy = 0, Mzz = 0, Mxy = 0, Mxz = 0, Myz = 0, Px = 0, Py = 0, Pz = 0;
                     if (c0 >= 0) {
-                        double dx = min_image(cxc - s_px[c0], Lx, hLx), dy = min_image(cyc - s_py[c0], Ly, hLy),
-                               dz = min_image(czc - s_pz[c0], Lz, hLz), vx, vy, vz;
-                        particle_velocity(c0, dx, dy, dz, s_ux, s_uy, s_uz, s_ox, s_oy, s_oz, vx, vy, vz);
-                        R Vx = sc * (R)vx, Vy = sc * (R)vy, Vz = sc * (R)vz, Bs = (R)B0;
+                        R dx, dy, dz, Vx, Vy, Vz;
+                        slot_geometry<R>(c0, cxc, cyc, czc, Lx, hLx, Ly, hLy, Lz, hLz, s_px, s_py, s_pz, s_ux, s_uy,
+                                         s_uz, s_ox, s_oy, s_oz, sc, dx, dy, dz, Vx, Vy, Vz);
+                        const R Bs = (R)B0;
                         Bt = Bs;
                         A0 = Bs * (rho - k15 * (Vx * Vx + Vy * Vy + Vz * Vz));
                         Px = Bs * Vx; Py = Bs * Vy; Pz = Bs * Vz;
@@ -539,10 +547,10 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
                         Mxy = Px * Vy; Mxz = Px * Vz; Myz = Py * Vz;
                     }
                     if (c1 >= 0) {
-                        double dx = min_image(cxc - s_px[c1], Lx, hLx), dy = min_image(cyc - s_py[c1], Ly, hLy),
-                               dz = min_image(czc - s_pz[c1], Lz, hLz), vx, vy, vz;
-                        particle_velocity(c1, dx, dy, dz, s_ux, s_uy, s_uz, s_ox, s_oy, s_oz, vx, vy, vz);
-                        R Vx = sc * (R)vx, Vy = sc * (R)vy, Vz = sc * (R)vz, Bs = (R)B1;
+                        R dx, dy, dz, Vx, Vy, Vz;
+                        slot_geometry<R>(c1, cxc, cyc, czc, Lx, hLx, Ly, hLy, Lz, hLz, s_px, s_py, s_pz, s_ux, s_uy,
+                                         s_uz, s_ox, s_oy, s_oz, sc, dx, dy, dz, Vx, Vy, Vz);
+                        const R Bs = (R)B1;
                         Bt = Bt + Bs;
                         A0 = A0 + Bs * (rho - k15 * (Vx * Vx + Vy * Vy + Vz * Vz));
                         R qx = Bs * Vx, qy = Bs * Vy, qz = Bs * Vz;
@@ -588,17 +596,19 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
                     else if (pend1 == c) { Bs = B1; pend1 = -1; }
                     double v[6] = {0, 0, 0, 0, 0, 0};
                     if (Bs != 0.0) {
-                        double dx = min_image(cxc - s_px[c], Lx, hLx), dy = min_image(cyc - s_py[c], Ly, hLy),
-                               dz = min_image(czc - s_pz[c], Lz, hLz), vx, vy, vz;
-                        particle_velocity(c, dx, dy, dz, s_ux, s_uy, s_uz, s_ox, s_oy, s_oz, vx, vy, vz);
-                        R Vx = sc * (R)vx, Vy = sc * (R)vy, Vz = sc * (R)vz;
-                        if (S::SCALED) Bs *= (double)kp.h_inv;
-                        v[0] = Bs * (double)(hx - Vx);
-                        v[1] = Bs * (double)(hy - Vy);
-                        v[2] = Bs * (double)(hz - Vz);
-                        v[3] = dy * v[2] - dz * v[1];
-                        v[4] = dz * v[0] - dx * v[2];
-                        v[5] = dx * v[1] - dy * v[0];
+                        // this cell's share in the collision's precision; the
+                        // sums over cells and tiles are FP64
+                        R dx, dy, dz, Vx, Vy, Vz;
+                        slot_geometry<R>(c, cxc, cyc, czc, Lx, hLx, Ly, hLy, Lz, hLz, s_px, s_py, s_pz, s_ux, s_uy,
+                                         s_uz, s_ox, s_oy, s_oz, sc, dx, dy, dz, Vx, Vy, Vz);
+                        const R Bh = (R)(S::SCALED ? Bs * (double)kp.h_inv : Bs);
+                        const R fx = Bh * (hx - Vx), fy = Bh * (hy - Vy), fz = Bh * (hz - Vz);
+                        v[0] = (double)fx;
+                        v[1] = (double)fy;
+                        v[2] = (double)fz;
+                        v[3] = (double)(dy * fz - dz * fy);
+                        v[4] = (double)(dz * fx - dx * fz);
+                        v[5] = (double)(dx * fy - dy * fx);
                     }
                     int comp;
                     const double sum = wave_sum6(v, lane, comp);

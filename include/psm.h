@@ -55,7 +55,8 @@ enum psm_status {
 
 /* PDF storage. FP64 stores f and computes in FP64. The deviation forms store
  * d = f - w_q (FP16 as scale*d with a power-of-two scale) and compute the
- * collision in FP32; forces, torques and mass sums stay FP64. */
+ * collision and each cell's force and torque share in FP32; the force and
+ * torque sums over cells and the mass and momentum sums stay FP64. */
 enum psm_storage { PSM_FP64 = 0, PSM_FP32DEV = 1, PSM_FP16DEV = 2 };
 
 /* Boundary type of a z face (psm_box_desc.face_type). */

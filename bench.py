@@ -383,8 +383,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the engine has no multi-GPU path (one box per GPU would "
-              "shard by domain decomposition; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the engine has no multi-GPU path (it would shard the box by "
+              "domain decomposition across GPUs). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

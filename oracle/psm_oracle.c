@@ -19,8 +19,7 @@
  * the pre-collision PDF field. One step = map particles -> collide every cell
  * (eq. 17) and accumulate force/torque (eqs. 21-22) -> stream (eq. 2).
  *
- * Readings where the paper is silent or ambiguous (each one is also listed in
- * the design notes of the repository):
+ * Readings where the paper is silent or ambiguous:
  *   - D3Q19 velocity order and weights: the paper cites them only; the order
  *     below is the canonical I/O order of this project.
  *   - Forcing prefactor: eq. (8) is multiplied by (1 - 1/(2 tau)) (Guo et al.)

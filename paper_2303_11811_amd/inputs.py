@@ -222,7 +222,7 @@ def n_spheres_for_fraction(dims, phi, r):
 
 
 # ---------------------------------------------------------------------------
-# Workload recipes (sizes, seeds and distributions stated in the design notes)
+# Workload recipes: sizes, seeds and distributions of each benchmark and test workload
 
 def parity_32(seed=0):
     """32^3 periodic box, tau 0.6, Taylor-Green amplitude 0.01, 8 spheres of

@@ -292,3 +292,70 @@ def test_duct_flow_side_walls():
     assert np.allclose(w, w.T, rtol=0, atol=1e-15)
     assert np.allclose(w, w[::-1, :], rtol=0, atol=1e-15)
     assert np.all(w > 0)
+
+
+def _face_group_sums(rho0, V, g, tau):
+    """Sums over the five directions with c_z = +1 (s = +1) or -1 (s = -1) of
+    the state E(rho0, V), of its post-collision values (SRT with the Guo
+    forcing, g along z) and the post-collision velocity, derived by hand for
+    a uniform state. Over such a group, sum_q w_q = 1/6, sum_q w_q (c_q.U) =
+    s U_z/6 and sum_q w_q (c_q.U)^2 = (U_x^2 + U_y^2)/18 + U_z^2/6, so
+      sum_q E_q(rho, U) = rho/6 + s U_z/2 + U_z^2/2    (tangential parts cancel)
+      sum_q F_q         = (1 - 1/(2 tau)) g_z (s/2 + U_z),
+    with U = V + g/2 inside the collision (eq. 7) and j = V before it."""
+    pref = 1.0 - 1.0 / (2.0 * tau)
+    Uz = V[2] + 0.5 * g
+    out = {}
+    for s in (1, -1):
+        P = rho0 / 6.0 + s * V[2] / 2.0 + V[2] ** 2 / 2.0
+        E = rho0 / 6.0 + s * Uz / 2.0 + Uz ** 2 / 2.0
+        out[s] = P + (E - P) / tau + pref * g * (s / 2.0 + Uz)
+    return out
+
+
+@pytest.mark.parametrize("faces", ["velocity_in", "both_pressure"])
+@pytest.mark.parametrize("g", [2e-3, -1.5e-3])
+def test_pressure_face_first_step_mass_balance(faces, g):
+    """Which velocity the anti-bounce-back uses (R16: the boundary cell's
+    post-collision velocity j + g of the same step, not the pre-collision j
+    nor U = j + g/2) decides the mass that crosses a pressure face. Per face
+    cell and step the face rule returns f_qbar = -f~_q + 2 w_q (rho_w +
+    4.5 (c_q.u)^2 - 1.5 u.u) for the five leaving directions q, so the mass
+    leaving is 2 S - rho_w/3 - u_z^2 (S the sum of the leaving f~_q, and
+    sum_q w_q (4.5 (c_q.u)^2 - 1.5 u.u) = u_z^2/2 over the group). A velocity
+    face adds exactly u_wz per cell (sum of 6 w_q (c_q.u_w) over the group).
+    With a body force along the flow, the first step from a uniform E(rho0, V)
+    then changes the total mass by a closed form in which u_z = V_z + g; the
+    other two readings differ from it by N_xy (2 V_z g + g^2) and
+    N_xy (V_z g + g^2/4), far above round-off."""
+    tau, rho0 = 0.8, 1.01
+    V = np.array([0.01, -0.02, 0.04])
+    nx, ny, nz = 4, 5, 6
+    rho_top, rho_bot = 0.995, 1.004
+    uw = np.array([0.003, 0.001, 0.035])
+    if faces == "velocity_in":
+        box = oracle.Box(nx, ny, nz, tau=tau, fext=(0.0, 0.0, g), walls_z=True, wall_u=(uw, (0.0, 0.0, 0.0)),
+                         face_type=(oracle.FACE_VELOCITY, oracle.FACE_PRESSURE), face_rho=(1.0, rho_top))
+    else:
+        box = oracle.Box(nx, ny, nz, tau=tau, fext=(0.0, 0.0, g), walls_z=True,
+                         face_type=(oracle.FACE_PRESSURE, oracle.FACE_PRESSURE), face_rho=(rho_bot, rho_top))
+    f0 = oracle.equilibrium(box, np.repeat(V[:, None], box.N, axis=1), np.full(box.N, rho0))
+    f1 = oracle.run(box, f0, 1).f
+    dm = f1.sum() - f0.sum()
+
+    S = _face_group_sums(rho0, V, g, tau)
+    nxy = nx * ny
+
+    def expected(uz):
+        out_top = 2.0 * S[1] - rho_top / 3.0 - uz ** 2
+        if faces == "velocity_in":
+            into_bottom = uw[2]
+        else:
+            into_bottom = -(2.0 * S[-1] - rho_bot / 3.0 - uz ** 2)
+        return nxy * (into_bottom - out_top)
+
+    exact = expected(V[2] + g)
+    assert abs(dm - exact) < 1e-13 * f0.sum()
+    # the pre-collision readings would be told apart
+    for uz in (V[2], V[2] + 0.5 * g):
+        assert abs(expected(uz) - exact) > 1e6 * 1e-13 * f0.sum()

@@ -27,6 +27,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "psm_oracle.c")
 _LIB = os.path.join(_HERE, "libpsm_oracle.so")
+# timing build of the same source with OpenMP (the CPU baseline's all-core
+# figure); every test uses the plain build
+_LIB_OMP = os.path.join(_HERE, "libpsm_oracle_omp.so")
 
 NQ = 19
 MAP_LINEAR = 0
@@ -34,12 +37,14 @@ MAP_SUBSAMPLE = 1
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no fused multiply-add, plain -O2)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (no fused multiply-add, plain -O2), and the
+    OpenMP timing build of the same source."""
+    for lib, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+            tmp = lib + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", *extra,
+                                   "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, lib)
     return _LIB
 
 
@@ -51,17 +56,19 @@ class _Box(ctypes.Structure):
                 ("face_rho", ctypes.c_double * 2), ("walls_x", ctypes.c_int), ("walls_y", ctypes.c_int)]
 
 
-_lib = None
+_libs = {}
 _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.POINTER(ctypes.c_int)
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def _load(timing_build=False):
+    path = _LIB_OMP if timing_build else _LIB
+    if path not in _libs:
+        if not os.path.exists(path):
             build(force=False)
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
+        lib.psmo_threads.argtypes = [ctypes.c_int]
+        lib.psmo_threads.restype = ctypes.c_int
         lib.psmo_lattice.argtypes = [_I, _D, _I]
         lib.psmo_Va.argtypes = [ctypes.c_double]
         lib.psmo_Va.restype = ctypes.c_double
@@ -82,8 +89,14 @@ def _load():
         lib.psmo_run.restype = ctypes.c_longlong
         lib.psmo_integrate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _D, _D,
                                        _I, _D, _D, _D, _D, _D, _D, _D, _D, ctypes.c_int]
-        _lib = lib
-    return _lib
+        _libs[path] = lib
+    return _libs[path]
+
+
+def threads(n=0, timing_build=True) -> int:
+    """Set (n > 0) and return the thread count of the collide-and-stream loop
+    of the timing build; the plain build always reports 1."""
+    return int(_load(timing_build).psmo_threads(int(n)))
 
 
 def _dp(a):
@@ -232,9 +245,11 @@ class Result:
     __slots__ = ("f", "F", "T", "A", "B", "pid", "overflow")
 
 
-def run(box: Box, f0, nsteps, x=None, r=None, U=None, Om=None, frv=None) -> Result:
+def run(box: Box, f0, nsteps, x=None, r=None, U=None, Om=None, frv=None, timing_build=False) -> Result:
     """Advance f0 ([19][N], pre-collision) by nsteps. Returns the new field and
-    the last step's force, torque, force scale, slots and overflow count."""
+    the last step's force, torque, force scale, slots and overflow count.
+    timing_build: run the OpenMP build (same arithmetic per cell; force and
+    torque summed per thread, then over threads in order)."""
     f = _f64(f0, (NQ, box.N)).copy()
     if x is None or len(np.atleast_1d(r)) == 0:
         x = np.zeros((0, 3)); r = np.zeros(0); U = np.zeros((0, 3)); Om = np.zeros((0, 3))
@@ -251,7 +266,7 @@ def run(box: Box, f0, nsteps, x=None, r=None, U=None, Om=None, frv=None) -> Resu
     res.B = np.zeros((2, box.N))
     res.pid = np.zeros((2, box.N), dtype=np.int32)
     bc = box._c()
-    res.overflow = int(_load().psmo_run(ctypes.byref(bc), int(nsteps), np_, _dp(x), _dp(r),
+    res.overflow = int(_load(timing_build).psmo_run(ctypes.byref(bc), int(nsteps), np_, _dp(x), _dp(r),
                                         _dp(frv), _dp(U), _dp(Om), _dp(f), _dp(res.F),
                                         _dp(res.T), _dp(res.A), _dp(res.B), _ip(res.pid)))
     res.f = f

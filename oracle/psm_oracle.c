@@ -50,10 +50,18 @@
  *     boundary cell's post-collision velocity sum_q f~_q c_q of the same step.
  *
  * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared -o libpsm_oracle.so
+ * The same source built with -fopenmp is a timing build: the collide-and-
+ * stream loop of psmo_run is split over z-planes between threads, each thread
+ * sums the force and torque of its own cells (in cell order) and the thread
+ * sums are added in thread order. Built without OpenMP (the plain build every
+ * test uses) there is one such sum, so it is the cell-order sum itself.
  */
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NQ 19
 
@@ -102,6 +110,20 @@ typedef struct {
     const double *U;     /* (n,3) translational velocity */
     const double *Om;    /* (n,3) angular velocity */
 } psmo_particles;
+
+/* ------------------------------------------------------------------ */
+/* Threads of the collide-and-stream loop: the timing build (OpenMP) sets
+ * and reports them (n <= 0 keeps the current count); the plain build has 1. */
+int psmo_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ */
 /* Lattice export for the tests.                                        */
@@ -447,15 +469,31 @@ long long psmo_run(const psmo_box *b, int nsteps, int np, const double *x, const
     slot2 *slots = (slot2 *)malloc(sizeof(slot2) * (size_t)N);
     double *fnew = (double *)malloc(sizeof(double) * (size_t)NQ * (size_t)N);
     long long overflow = 0;
+    int nth = 1;
+#ifdef _OPENMP
+    nth = omp_get_max_threads();
+#endif
+    /* per-thread force, torque and force-scale sums: [thread][np][3], [thread][np] */
+    size_t np1 = np > 0 ? (size_t)np : 1;
+    double *Fth = (double *)malloc(sizeof(double) * 3 * np1 * (size_t)nth);
+    double *Tth = (double *)malloc(sizeof(double) * 3 * np1 * (size_t)nth);
+    double *Ath = (double *)malloc(sizeof(double) * np1 * (size_t)nth);
 
     for (int step = 0; step < nsteps; ++step) {
         overflow = 0;
         map_all(b, &P, slots, &overflow);
-        for (int p = 0; p < np; ++p) {
-            for (int a = 0; a < 3; ++a) { F[3 * p + a] = 0.0; T[3 * p + a] = 0.0; }
-            if (Ascale) Ascale[p] = 0.0;
-        }
-        for (int k = 0; k < nz; ++k)
+        for (size_t e = 0; e < 3 * np1 * (size_t)nth; ++e) { Fth[e] = 0.0; Tth[e] = 0.0; }
+        for (size_t e = 0; e < np1 * (size_t)nth; ++e) Ath[e] = 0.0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+        for (int k = 0; k < nz; ++k) {
+            int th = 0;
+#ifdef _OPENMP
+            th = omp_get_thread_num();
+#endif
+            double *Fs = Fth + 3 * np1 * (size_t)th, *Ts = Tth + 3 * np1 * (size_t)th;
+            double *As = Ascale ? Ath + np1 * (size_t)th : NULL;
             for (int j = 0; j < ny; ++j)
                 for (int i = 0; i < nx; ++i) {
                     long n = i + (long)nx * (j + (long)ny * k);
@@ -470,12 +508,12 @@ long long psmo_run(const psmo_box *b, int nsteps, int np, const double *x, const
                         for (int a = 0; a < 3; ++a) Bg[a] = s->B[t] * g[3 * t + a];
                         cross(d + 3 * t, Bg, tq);
                         for (int a = 0; a < 3; ++a) {
-                            F[3 * p + a] += Bg[a];
-                            T[3 * p + a] += tq[a];
+                            Fs[3 * p + a] += Bg[a];
+                            Ts[3 * p + a] += tq[a];
                         }
-                        if (Ascale)
-                            Ascale[p] += s->B[t] * sqrt(g[3 * t] * g[3 * t] + g[3 * t + 1] * g[3 * t + 1] +
-                                                        g[3 * t + 2] * g[3 * t + 2]);
+                        if (As)
+                            As[p] += s->B[t] * sqrt(g[3 * t] * g[3 * t] + g[3 * t + 1] * g[3 * t + 1] +
+                                                    g[3 * t + 2] * g[3 * t + 2]);
                     }
                     /* eq. (2): f_q(x + c_q, t + 1) = ft_q(x, t) */
                     for (int q = 0; q < NQ; ++q) {
@@ -510,8 +548,28 @@ long long psmo_run(const psmo_box *b, int nsteps, int np, const double *x, const
                         fnew[q * N + ii + (long)nx * (jj + (long)ny * kk)] = ft[q];
                     }
                 }
+        }
+        for (int p = 0; p < np; ++p) {
+            for (int a = 0; a < 3; ++a) {
+                double fs = 0.0, ts = 0.0;
+                for (int th = 0; th < nth; ++th) {
+                    fs += Fth[3 * np1 * (size_t)th + 3 * p + a];
+                    ts += Tth[3 * np1 * (size_t)th + 3 * p + a];
+                }
+                F[3 * p + a] = fs;
+                T[3 * p + a] = ts;
+            }
+            if (Ascale) {
+                double as = 0.0;
+                for (int th = 0; th < nth; ++th) as += Ath[np1 * (size_t)th + p];
+                Ascale[p] = as;
+            }
+        }
         memcpy(f, fnew, sizeof(double) * (size_t)NQ * (size_t)N);
     }
+    free(Fth);
+    free(Tth);
+    free(Ath);
 
     if (Bout && pidout) {
         for (long n = 0; n < N; ++n)

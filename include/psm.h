@@ -16,7 +16,12 @@
  * - Status: every call returns 0 (PSM_OK) or a negative PSM_E* code and never
  *   throws. psm_last_error() returns a thread-local text of the last failure.
  * - Argument checks happen on the host before anything is enqueued; a bad
- *   argument returns PSM_EINVAL and leaves the context unchanged.
+ *   argument returns PSM_EINVAL and leaves the context unchanged. What only
+ *   the device can see (a cell index given in device memory, tile lists built
+ *   on the device, a third sphere overlapping a cell) sets a device error
+ *   word that the next synchronising call of the context (psm_get_forces,
+ *   psm_get_stats, psm_get_particles) reports and clears; the kernels stay in
+ *   bounds meanwhile.
  * - Lattice units: dx = dt = 1, rho_0 = 1, c_s^2 = 1/3. Boxes are periodic
  *   along every axis without walls (psm_box_desc.walls_x, walls_y, walls_z).
  * - Cells: index n = x + nx*(y + ny*z); cell (i,j,k) has its centre at
@@ -50,6 +55,7 @@ enum psm_status {
     PSM_EHIP = -2,        /* a HIP runtime call failed; text kept in psm_last_error */
     PSM_ECAPACITY = -3,   /* more particles / tile candidates than the context holds */
     PSM_ENONFINITE = -4,  /* non-finite mass or momentum found by psm_get_stats */
+    PSM_EDRIFT = -5,      /* mass drifted beyond the tolerance of psm_set_drift_check */
     PSM_ESTATE = -6       /* call not valid in the current state */
 };
 
@@ -117,9 +123,10 @@ int psm_set_pdfs(psm_ctx* ctx, int box, const double* f);
 /* Read the pre-collision PDFs f(x,t) of box `box` into f: device [19][N] FP64. */
 int psm_get_pdfs(psm_ctx* ctx, int box, double* f);
 
-/* Read f(x,t) at ncells cells. cells: device [ncells] int cell indices (each
- * in [0,N), else PSM_EINVAL is not detected on the device: the caller checks);
- * out: device [19][ncells] FP64. */
+/* Read f(x,t) at ncells cells. cells: device [ncells] int cell indices, each
+ * in [0,N); out: device [19][ncells] FP64. The indices are only visible to the
+ * device: an index outside [0,N) reads nothing, its 19 outputs are NaN, and
+ * the next synchronising call returns PSM_EINVAL. */
 int psm_get_pdfs_at(psm_ctx* ctx, int box, int ncells, const int* cells, double* out);
 
 /* Density and velocity of eqs. (6)-(7) (U includes the f^ext/2 shift).
@@ -131,13 +138,14 @@ int psm_get_macroscopic(psm_ctx* ctx, int box, double* rho, double* u);
  * omega (n,3) (NULL omega = 0); they are copied before the call returns.
  * Positions are wrapped into the box. Radii must lie in [1, max_radius]; along
  * an axis with walls every centre needs r + 1 <= x_a <= n_a - r - 1. The
- * library computes f(r) of eq. (26) in FP64 and uploads through pinned staging
- * (asynchronous). When positions or radii differ from the previous call it
- * rebuilds the per-tile candidate lists, which synchronises and returns
- * PSM_ECAPACITY if a tile would list more candidates than the kernel stages
- * (the context then refuses to step until a valid set is given).
- * PSM_ECAPACITY also if n > max_particles. psm_get_forces and psm_get_stats
- * also report a device-side list overflow after psm_integrate. */
+ * library computes f(r) of eq. (26) in FP64 and uploads through pinned staging.
+ * When positions or radii differ from the previous call it rebuilds the
+ * per-tile candidate lists on the device. Nothing waits for the device: if
+ * a tile would list more candidates than the kernel stages, its list is cut
+ * (the steps stay in bounds, their results are not valid) and the next
+ * synchronising call returns PSM_ECAPACITY, after which the context refuses
+ * to step until a valid set is given. PSM_ECAPACITY at once if
+ * n > max_particles. */
 int psm_set_particles(psm_ctx* ctx, int box, int n, const double* x, const double* r,
                       const double* U, const double* omega);
 
@@ -149,7 +157,8 @@ int psm_step(psm_ctx* ctx, int nsteps);
 
 /* Hydrodynamic force and torque of eqs. (21)-(22) on every sphere of box
  * `box` from the last executed step. F, T: host (n,3) FP64 (n = particles set).
- * Synchronises. Before any step: zeros. */
+ * Synchronises and reports the device error word (see the conventions). Before
+ * any step: zeros. */
 int psm_get_forces(psm_ctx* ctx, int box, double* F, double* T);
 
 /* Solid fractions of the current particles (same device mapping as the step):
@@ -161,8 +170,29 @@ int psm_get_solid_fraction(psm_ctx* ctx, int box, double* B, int* pid);
 /* FP64 totals of the current state of box `box`: mass sum_x sum_q f,
  * momentum sum_x sum_q f c_q (host double[3], may be NULL), and the number of
  * dropped third-or-later overlaps of the current mapping (may be NULL).
- * Synchronises. PSM_ENONFINITE if mass or momentum is not finite. */
+ * Synchronises and reports the device error word. PSM_ENONFINITE if mass or
+ * momentum is not finite; PSM_EDRIFT (outputs still written) if the drift
+ * check of the box is on and the mass moved away from its reference. */
 int psm_get_stats(psm_ctx* ctx, int box, double* mass, double* momentum, long long* slot_overflows);
+
+/* Mass drift watchdog of box `box`. The method conserves mass (eq. 2 moves
+ * populations, eqs. 3, 8 and 19 add none), so in a periodic or closed box
+ * the FP64 mass changes only by rounding. With rel_tol > 0, the first
+ * psm_get_stats after this call or after psm_set_equilibrium/psm_set_pdfs
+ * records the mass as reference, and later calls return PSM_EDRIFT when
+ * |mass - reference| > rel_tol |reference|. rel_tol = 0 turns it off.
+ * PSM_EINVAL for a box with a pressure face or a face with a normal wall
+ * velocity (they exchange mass). Host-only call. */
+int psm_set_drift_check(psm_ctx* ctx, int box, double rel_tol);
+
+/* Strict-slot mode (Sec. 3.1.1 keeps at most two solid fractions per cell).
+ * Off (the default, or the environment variable PSM_STRICT_SLOTS unset or
+ * not "1" at psm_create): a third overlap of a cell is dropped (the two
+ * strongest stay) and counted by psm_get_stats. On: a step that meets such a
+ * cell still runs the same way, and the next synchronising call returns
+ * PSM_ECAPACITY; the context then refuses to step until psm_set_particles.
+ * Overlaps met before the switch are forgotten. Synchronises. */
+int psm_set_strict_slots(psm_ctx* ctx, int enable);
 
 /* Sphere dynamics (Sec. 2.2.2) on the device, for collision-free spheres.
  * m = rho_p (4/3) pi r^3 and I = (2/5) m r^2 (fluid density 1); the total force

@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpsm.so")
 
-PSM_OK, PSM_EINVAL, PSM_EHIP, PSM_ECAPACITY, PSM_ENONFINITE, PSM_ESTATE = 0, -1, -2, -3, -4, -6
+PSM_OK, PSM_EINVAL, PSM_EHIP, PSM_ECAPACITY, PSM_ENONFINITE, PSM_EDRIFT, PSM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PSM_FP64, PSM_FP32DEV, PSM_FP16DEV = 0, 1, 2
 PSM_MAP_LINEAR, PSM_MAP_SUBSAMPLE = 0, 1
 PSM_LAUNCH_PERSISTENT, PSM_LAUNCH_FILTER = 1, 2
@@ -62,6 +62,8 @@ _SIGS = {
     "psm_get_forces": ([_P, ctypes.c_int, _D, _D], ctypes.c_int),
     "psm_get_solid_fraction": ([_P, ctypes.c_int, _P, _P], ctypes.c_int),
     "psm_get_stats": ([_P, ctypes.c_int, _D, _D, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+    "psm_set_drift_check": ([_P, ctypes.c_int, ctypes.c_double], ctypes.c_int),
+    "psm_set_strict_slots": ([_P, ctypes.c_int], ctypes.c_int),
     "psm_set_launch": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "psm_get_launch": ([_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
@@ -231,6 +233,14 @@ def psm_get_stats(ctx, box):
     return mass.value, mom, int(ov.value)
 
 
+def psm_set_drift_check(ctx, box, rel_tol):
+    return _check(lib().psm_set_drift_check(ctx, box, float(rel_tol)))
+
+
+def psm_set_strict_slots(ctx, enable):
+    return _check(lib().psm_set_strict_slots(ctx, int(bool(enable))))
+
+
 def psm_set_launch(ctx, tx, ty, tz, flags=0):
     return _check(lib().psm_set_launch(ctx, int(tx), int(ty), int(tz), int(flags)))
 
@@ -398,6 +408,12 @@ class Engine:
 
     def get_stats(self, box=0):
         return psm_get_stats(self.ctx, box)
+
+    def set_drift_check(self, box, rel_tol):
+        psm_set_drift_check(self.ctx, box, rel_tol)
+
+    def set_strict_slots(self, enable):
+        psm_set_strict_slots(self.ctx, enable)
 
     def set_launch(self, tx, ty, tz, flags=0):
         psm_set_launch(self.ctx, tx, ty, tz, flags)

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -95,9 +96,10 @@ static int validate(const psm_box_desc* boxes, int nbox, int storage) {
         if (d.nx < 4 || d.ny < 4 || d.nz < 4) return fail(PSM_EINVAL, "box %d: every dimension must be >= 4", b);
         long long N = (long long)d.nx * d.ny * d.nz;
         if (N > 0x7fffffffLL) return fail(PSM_EINVAL, "box %d: more than 2^31-1 cells", b);
-        // byte offsets inside a z-plane are 32-bit
-        if ((long long)row_pitch(d.nx) * d.ny * NQ * 8 + 64LL * NQ * 8 >= (1LL << 32))
-            return fail(PSM_EINVAL, "box %d: z-planes larger than 2^32 bytes", b);
+        // byte offsets inside a z-plane are computed in 32-bit signed integers
+        // (with the padding to whole 64-cell blocks, FP64 storage bound)
+        if ((long long)row_pitch(d.nx) * d.ny * NQ * 8 + 64LL * NQ * 8 >= (1LL << 31))
+            return fail(PSM_EINVAL, "box %d: z-planes of 2^31 bytes or more (nx * ny too large)", b);
         if (!(d.tau > 0.5) || !std::isfinite(d.tau)) return fail(PSM_EINVAL, "box %d: tau must be > 1/2", b);
         for (int a = 0; a < 3; ++a)
             if (!std::isfinite(d.fext[a])) return fail(PSM_EINVAL, "box %d: non-finite body force", b);
@@ -205,7 +207,9 @@ struct psm_ctx {
     int grid = 0;
     int parity = 0;
     bool have_particles_lists = false;
-    bool lists_unchecked = false;   // rebuilt on the device after an integration
+    bool strict_slots = false;      // a third overlap in a cell is an error
+    // mass drift check per box: relative tolerance (0 = off) and reference mass (NaN = not taken)
+    std::vector<double> drift_tol, ref_mass;
     // device pointers into the workspace
     BoxDev* d_boxes = nullptr;
     int* d_tbase = nullptr;
@@ -213,7 +217,9 @@ struct psm_ctx {
     Particles P{};
     int *d_tcnt = nullptr, *d_toff = nullptr, *d_tpid = nullptr;
     double* d_partial = nullptr;
-    int* d_misc = nullptr;               // [0..1] bin stats, [8..9] dropped (u64), [16] device errors
+    int* d_misc = nullptr;               // [0..1] bin stats, [8..9] dropped (u64), [16] device error word
+    int* d_flags = nullptr;              // d_misc + 16 (FLAG_* bits)
+    int* h_flags = nullptr;              // pinned copy of the device error word
     double* d_statpart = nullptr;
     int* d_scan = nullptr;               // scan scratch (chunk sums and maxima)
     // last uploaded positions and radii per box: unchanged geometry keeps the lists
@@ -307,7 +313,8 @@ static int rebuild_lists(psm_ctx* c) {
     HIP_TRY(launch_bin(bp, c->d_misc, c->d_scan, c->stream));
     int stats[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(stats, c->d_misc, sizeof stats, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(launch_fill_int(c->d_misc + 16, 1, 0, c->stream));   // earlier device-side flags are void
+    // list flags of earlier builds are void; this build reports its own here
+    HIP_TRY(launch_check_lists(c->d_misc, c->L.cap_max, c->d_flags, 0, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (stats[1] > c->L.cap_max)
         return fail(PSM_ECAPACITY, "tile lists need %d entries, capacity %lld", stats[1], c->L.cap_max);
@@ -316,13 +323,12 @@ static int rebuild_lists(psm_ctx* c) {
                     stats[0], MAXC);
     HIP_TRY(launch_bin_fill(bp, c->stream));
     c->have_particles_lists = true;
-    c->lists_unchecked = false;
     return PSM_OK;
 }
 
 // Rebuild the lists without waiting for the device: the counts are checked on
-// the device, which flags an overflow in d_misc[16] (the fill and the step
-// kernel stay in bounds); synchronising calls report it.
+// the device, which replaces the list bits of the error word (the fill and the
+// step kernel stay in bounds on capped lists); synchronising calls report them.
 static int rebuild_lists_async(psm_ctx* c) {
     BinParams bp;
     bp.boxes = c->d_boxes;
@@ -336,29 +342,44 @@ static int rebuild_lists_async(psm_ctx* c) {
     bp.ts = c->ts;
     bp.cap = c->L.cap_max;
     HIP_TRY(launch_bin(bp, c->d_misc, c->d_scan, c->stream));
-    HIP_TRY(launch_check_lists(c->d_misc, c->L.cap_max, c->d_misc + 16, c->stream));
+    HIP_TRY(launch_check_lists(c->d_misc, c->L.cap_max, c->d_flags, 1, c->stream));
     HIP_TRY(launch_bin_fill(bp, c->stream));
-    c->lists_unchecked = true;
+    c->have_particles_lists = true;
     return PSM_OK;
 }
 
-// After a synchronisation: report (and clear) an overflow flagged by the
-// device since lists were last rebuilt there. The context then refuses to
-// step until psm_set_particles gives a valid set.
-static int device_errors(psm_ctx* c) {
-    if (!c->lists_unchecked) return PSM_OK;
-    int* e = (int*)(c->h_read + 9 * (size_t)std::max(c->P_total, 1));
-    HIP_TRY(hipMemcpyAsync(e, c->d_misc + 16, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+// Every synchronising call copies the device error word with its read-back
+// (sync_with_flags) and reports it afterwards (take_flags), which clears the
+// word on the device. A list overflow (device-built lists) or, in strict-slot
+// mode, a third overlap makes the context refuse to step until
+// psm_set_particles; a bad psm_get_pdfs_at index is an argument error.
+static int sync_with_flags(psm_ctx* c) {
+    HIP_TRY(hipMemcpyAsync(c->h_flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    if (*e == 0) return PSM_OK;
-    int flags = *e;
-    *e = 0;
-    HIP_TRY(hipMemcpyAsync(c->d_misc + 16, e, sizeof(int), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    c->have_particles_lists = false;
-    c->lists_unchecked = false;
-    if (flags & 1) return fail(PSM_ECAPACITY, "moved spheres need more tile-list entries than the context holds");
-    return fail(PSM_ECAPACITY, "moved spheres put more than %d candidates into a tile: use a smaller tile shape", MAXC);
+    return PSM_OK;
+}
+
+static int take_flags(psm_ctx* c) {
+    const int f = *c->h_flags;
+    if (f == 0) return PSM_OK;
+    *c->h_flags = 0;
+    HIP_TRY(launch_fill_int(c->d_flags, 1, 0, c->stream));
+    if (f & FLAG_LIST_ENTRIES) {
+        c->have_particles_lists = false;
+        return fail(PSM_ECAPACITY, "the spheres need more tile-list entries than the context holds");
+    }
+    if (f & FLAG_LIST_TILE) {
+        c->have_particles_lists = false;
+        return fail(PSM_ECAPACITY, "the spheres put more than %d candidates into a tile: use a smaller tile shape",
+                    MAXC);
+    }
+    if ((f & FLAG_SLOT_OVERFLOW) && c->strict_slots) {
+        c->have_particles_lists = false;
+        return fail(PSM_ECAPACITY, "strict slots: a cell is overlapped by more than two spheres");
+    }
+    if (f & FLAG_BAD_CELL)
+        return fail(PSM_EINVAL, "psm_get_pdfs_at: a cell index was outside the box (those outputs are NaN)");
+    return PSM_OK;
 }
 
 extern "C" int psm_workspace_size(const psm_box_desc* boxes, int nbox, int storage, size_t* bytes) {
@@ -471,6 +492,7 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
     c->d_tpid = (int*)(c->ws + L.off_tpid);
     c->d_partial = (double*)(c->ws + L.off_partial);
     c->d_misc = (int*)(c->ws + L.off_misc);
+    c->d_flags = c->d_misc + 16;
     c->d_statpart = (double*)(c->ws + L.off_statpart);
     c->d_scan = (int*)(c->ws + L.off_scan);
     c->last_xr.assign(nbox, std::vector<double>());
@@ -484,6 +506,14 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
     hip_ok(hipHostMalloc((void**)&c->h_stage, sizeof(double) * c->h_stage_n, hipHostMallocDefault), "hipHostMalloc");
     if (err) { delete c; return err; }
     c->h_read = c->h_stage + 2 * c->h_half;
+    c->h_flags = (int*)(c->h_read + 9 * P1);   // inside the read area's padding
+    *c->h_flags = 0;
+    {
+        const char* e = std::getenv("PSM_STRICT_SLOTS");
+        c->strict_slots = e && std::strcmp(e, "1") == 0;
+    }
+    c->drift_tol.assign(nbox, 0.0);
+    c->ref_mass.assign(nbox, std::nan(""));
     for (int h = 0; h < 2; ++h) hip_ok(hipEventCreateWithFlags(&c->stage_ev[h], hipEventDisableTiming), "event");
     if (err) { (void)hipHostFree(c->h_stage); delete c; return err; }
     c->last_r.assign(nbox, std::vector<double>());
@@ -537,6 +567,7 @@ extern "C" int psm_set_equilibrium(psm_ctx* c, int box, const double* rho, const
     if (rc) return rc;
     if (!u) return fail(PSM_EINVAL, "u is NULL");
     HIP_TRY(launch_set_equilibrium(c->storage, c->box[box], c->parity, rho, u, c->h_scale, c->stream));
+    c->ref_mass[box] = std::nan("");   // a new state: the drift reference is taken again
     return PSM_OK;
 }
 
@@ -545,6 +576,7 @@ extern "C" int psm_set_pdfs(psm_ctx* c, int box, const double* f) {
     if (rc) return rc;
     if (!f) return fail(PSM_EINVAL, "f is NULL");
     HIP_TRY(launch_set_pdfs(c->storage, c->box[box], c->parity, f, c->h_scale, c->stream));
+    c->ref_mass[box] = std::nan("");   // a new state: the drift reference is taken again
     return PSM_OK;
 }
 
@@ -562,7 +594,8 @@ extern "C" int psm_get_pdfs_at(psm_ctx* c, int box, int ncells, const int* cells
     if (ncells < 0) return fail(PSM_EINVAL, "ncells < 0");
     if (ncells == 0) return PSM_OK;
     if (!cells || !out) return fail(PSM_EINVAL, "cells/out is NULL");
-    HIP_TRY(launch_get_pdfs_at(c->storage, c->box[box], c->parity, cells, ncells, out, c->h_inv, c->stream));
+    HIP_TRY(launch_get_pdfs_at(c->storage, c->box[box], c->parity, cells, ncells, out, c->h_inv, c->d_flags,
+                               c->stream));
     return PSM_OK;
 }
 
@@ -663,11 +696,13 @@ extern "C" int psm_set_particles(psm_ctx* c, int box, int n, const double* x, co
     c->box[box].np = n;
     c->np[box] = n;
     if (same_geometry) return PSM_OK;
-    std::vector<double> xr((size_t)4 * n);
+    std::vector<double>& xr = c->last_xr[box];
+    xr.resize((size_t)4 * n);
     for (int k = 0; k < 4; ++k) std::memcpy(xr.data() + (size_t)k * n, st + (size_t)k * m, sizeof(double) * n);
-    c->last_xr[box].swap(xr);
-    rc = rebuild_lists(c);
-    if (rc != PSM_OK) c->last_xr[box].clear();
+    // lists rebuilt on the device without waiting: an overflow is reported by
+    // the next synchronising call
+    rc = rebuild_lists_async(c);
+    if (rc != PSM_OK) xr.clear();
     return rc;
 }
 
@@ -684,6 +719,7 @@ static int step_params(psm_ctx* c, int parity, StepParams& kp) {
     kp.parity = parity;
     kp.h_scale = c->h_scale;
     kp.h_inv = c->h_inv;
+    kp.flags = c->d_flags;
     return PSM_OK;
 }
 
@@ -773,14 +809,12 @@ extern "C" int psm_get_forces(psm_ctx* c, int box, double* F, double* T) {
     int rc = check_box(c, box);
     if (rc) return rc;
     int n = c->np[box];
-    if (n == 0) return PSM_OK;
+    if (n == 0) return (rc = sync_with_flags(c)) ? rc : take_flags(c);
     if (!F || !T) return fail(PSM_EINVAL, "F/T is NULL");
     double* st = c->h_read;
     HIP_TRY(hipMemcpyAsync(st, c->P.acc + 6LL * c->box[box].part_base, sizeof(double) * 6 * n,
                            hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    rc = device_errors(c);
-    if (rc) return rc;
+    if ((rc = sync_with_flags(c)) || (rc = take_flags(c))) return rc;
     for (int p = 0; p < n; ++p)
         for (int a = 0; a < 3; ++a) {
             F[3 * p + a] = st[6 * p + a];
@@ -810,9 +844,7 @@ extern "C" int psm_get_stats(psm_ctx* c, int box, double* mass, double* momentum
     double* st = c->h_read;
     HIP_TRY(hipMemcpyAsync(st, out, sizeof(double) * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(st + 4, dropped, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    rc = device_errors(c);
-    if (rc) return rc;
+    if ((rc = sync_with_flags(c)) || (rc = take_flags(c))) return rc;
     if (mass) *mass = st[0];
     if (momentum)
         for (int a = 0; a < 3; ++a) momentum[a] = st[1 + a];
@@ -821,6 +853,46 @@ extern "C" int psm_get_stats(psm_ctx* c, int box, double* mass, double* momentum
     if (slot_overflows) *slot_overflows = (long long)dr;
     for (int k = 0; k < 4; ++k)
         if (!std::isfinite(st[k])) return fail(PSM_ENONFINITE, "box %d: non-finite mass or momentum", box);
+    if (c->drift_tol[box] > 0.0) {
+        // the first totals after the check is enabled or the state is set are the reference
+        if (std::isnan(c->ref_mass[box])) {
+            c->ref_mass[box] = st[0];
+        } else {
+            const double ref = c->ref_mass[box], rel = std::fabs(st[0] - ref) / std::fabs(ref);
+            if (!(rel <= c->drift_tol[box]))
+                return fail(PSM_EDRIFT, "box %d: mass %.17g drifted from %.17g by %.3g (relative), above %.3g", box,
+                            st[0], ref, rel, c->drift_tol[box]);
+        }
+    }
+    return PSM_OK;
+}
+
+extern "C" int psm_set_drift_check(psm_ctx* c, int box, double rel_tol) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return fail(PSM_EINVAL, "rel_tol must be >= 0 and finite");
+    const psm_box_desc& d = c->desc[box];
+    if (rel_tol > 0.0 && d.walls_z)
+        for (int w = 0; w < 2; ++w)
+            if (d.face_type[w] == PSM_FACE_PRESSURE || d.wall_u[w][2] != 0.0)
+                return fail(PSM_EINVAL, "box %d: a pressure face or a face with a normal velocity exchanges mass; "
+                                        "the drift check needs a closed or periodic box", box);
+    c->drift_tol[box] = rel_tol;
+    c->ref_mass[box] = std::nan("");
+    return PSM_OK;
+}
+
+extern "C" int psm_set_strict_slots(psm_ctx* c, int enable) {
+    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    // overlaps seen before the switch do not count
+    HIP_TRY(hipMemcpyAsync(c->h_flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (*c->h_flags & FLAG_SLOT_OVERFLOW) {
+        *c->h_flags &= ~FLAG_SLOT_OVERFLOW;
+        HIP_TRY(launch_fill_int(c->d_flags, 1, *c->h_flags, c->stream));
+    }
+    *c->h_flags = 0;
+    c->strict_slots = enable != 0;
     return PSM_OK;
 }
 
@@ -868,7 +940,6 @@ extern "C" int psm_integrate(psm_ctx* c, double dt, int scheme) {
     rc = enqueue_integrate(c, dt, scheme);
     // the host copies of positions are stale from here on
     for (auto& v : c->last_xr) v.clear();
-    c->lists_unchecked = true;
     return rc;
 }
 
@@ -920,10 +991,8 @@ extern "C" int psm_run(psm_ctx* c, int nsteps, double dt, int scheme) {
         if (rc == PSM_OK) rc = enqueue_integrate(c, dt, scheme);
         if (rc) return rc;
     }
-    if (nsteps > 0) {
+    if (nsteps > 0)
         for (auto& v : c->last_xr) v.clear();
-        c->lists_unchecked = true;
-    }
     return PSM_OK;
 }
 
@@ -931,8 +1000,7 @@ extern "C" int psm_get_particles(psm_ctx* c, int box, double* x, double* U, doub
     int rc = check_box(c, box);
     if (rc) return rc;
     int n = c->np[box];
-    if (n == 0) return PSM_OK;
-    if (!x && !U && !omega) return PSM_OK;
+    if (n == 0 || (!x && !U && !omega)) return (rc = sync_with_flags(c)) ? rc : take_flags(c);
     size_t P1 = (size_t)std::max(c->P_total, 1);
     int pb = c->box[box].part_base;
     // columns x y z (0-2), ux uy uz (5-7), ox oy oz (8-10) of the device table
@@ -941,9 +1009,7 @@ extern "C" int psm_get_particles(psm_ctx* c, int box, double* x, double* U, doub
                              hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpy2DAsync(st + 3 * (size_t)n, sizeof(double) * n, c->P.ux + pb, sizeof(double) * P1,
                              sizeof(double) * n, 6, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    rc = device_errors(c);
-    if (rc) return rc;
+    if ((rc = sync_with_flags(c)) || (rc = take_flags(c))) return rc;
     double* outs[3] = {x, U, omega};
     for (int k = 0; k < 3; ++k) {
         if (!outs[k]) continue;

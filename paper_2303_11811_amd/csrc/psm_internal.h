@@ -251,6 +251,7 @@ struct StepParams {
     int tx, ty, tz;
     int parity;
     float h_scale, h_inv;       // FP16 storage scale and its inverse (1 otherwise)
+    int* flags;                 // device error word: |= FLAG_SLOT_OVERFLOW when a cell meets a third sphere
 };
 
 struct ReduceParams {
@@ -299,7 +300,7 @@ hipError_t launch_set_equilibrium(int storage, const BoxDev& bx, int parity, con
                                   float scale, hipStream_t st);
 hipError_t launch_get_pdfs(int storage, const BoxDev& bx, int parity, double* f, float inv, hipStream_t st);
 hipError_t launch_get_pdfs_at(int storage, const BoxDev& bx, int parity, const int* cells, int ncells, double* out,
-                              float inv, hipStream_t st);
+                              float inv, int* flags, hipStream_t st);
 hipError_t launch_macroscopic(int storage, const BoxDev& bx, int parity, double* rho, double* u, float inv,
                               hipStream_t st);
 hipError_t launch_map_dense(const BoxDev& bx, const Particles& P, const int* tile_off, const int* tile_pid,
@@ -309,8 +310,18 @@ hipError_t launch_stats(int storage, const BoxDev& bx, int parity, float inv, do
                         hipStream_t st);
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 hipError_t launch_integrate(int scheme, const IntParams& ip, hipStream_t st);
-// err |= 1 if the lists need more than cap entries, |= 2 if a tile lists more than MAXC spheres
-hipError_t launch_check_lists(const int* stats, long long cap, int* err, hipStream_t st);
+// Bits of the device error word of a context, set by kernels and read and
+// cleared by the host at its next synchronising call.
+enum {
+    FLAG_LIST_ENTRIES = 1,    // the tile lists need more entries than the context holds
+    FLAG_LIST_TILE = 2,       // a tile lists more than MAXC spheres
+    FLAG_SLOT_OVERFLOW = 4,   // a step met a cell overlapped by more than two spheres
+    FLAG_BAD_CELL = 8         // psm_get_pdfs_at was given a cell index outside the box
+};
+// Replace the list bits of err: FLAG_LIST_ENTRIES if the lists need more than
+// cap entries, FLAG_LIST_TILE if a tile lists more than MAXC spheres (report =
+// 0: clear the list bits only)
+hipError_t launch_check_lists(const int* stats, long long cap, int* err, int report, hipStream_t st);
 hipError_t launch_fill_int(int* a, long long n, int v, hipStream_t st);
 
 }  // namespace psm

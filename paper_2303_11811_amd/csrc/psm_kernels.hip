@@ -407,6 +407,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
             // with the filter, only the candidates that can reach this wave at this z
             int c0 = -1, c1 = -1;
             double B0 = 0.0, B1 = 0.0;
+            int dropped = 0;   // overlaps beyond the two slots at this cell
 #define PSM_MAP_ONE(c)                                                                                       \
     do {                                                                                                    \
         double dx = min_image(cxc - s_px[c], Lx, hLx);                                                      \
@@ -429,7 +430,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
                         }
                         slots_finish(sl);
                     }
-                    c0 = sl.c0; c1 = sl.c1; B0 = sl.B0; B1 = sl.B1;
+                    c0 = sl.c0; c1 = sl.c1; B0 = sl.B0; B1 = sl.B1; dropped = sl.dropped;
                 }
             } else if (nc > 0) {
                 Slots sl;
@@ -438,10 +439,13 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
                     for (int c = 0; c < nc; ++c) PSM_MAP_ONE(c);
                     slots_finish(sl);
                 }
-                c0 = sl.c0; c1 = sl.c1; B0 = sl.B0; B1 = sl.B1;
+                c0 = sl.c0; c1 = sl.c1; B0 = sl.B0; B1 = sl.B1; dropped = sl.dropped;
             }
 #undef PSM_MAP_ONE
             const bool psm_wave = __ballot(c0 >= 0) != 0ull;
+            // a third overlap is dropped (the two strongest slots stay) and flagged
+            // once per wave; the host reports it in strict-slot mode
+            if (psm_wave && __ballot(dropped != 0) != 0ull && lane == 0) atomicOr(kp.flags, FLAG_SLOT_OVERFLOW);
 
             // 2. pull: f_q(x) = grid[q][x - c_q]
             R hx = 0, hy = 0, hz = 0;   // 2 j - U, for the force of eq. (21)
@@ -961,10 +965,16 @@ __global__ void k_get_pdfs(BoxDev bx, int parity, double* __restrict__ f, float 
 
 template <class S>
 __global__ void k_get_pdfs_at(BoxDev bx, int parity, const int* __restrict__ cells, int ncells,
-                              double* __restrict__ out, float inv) {
+                              double* __restrict__ out, float inv, int* __restrict__ flags) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ncells) return;
     long long n = cells[i];
+    if (n < 0 || n >= bx.N) {
+        // an index outside the box reads nothing: NaN out, flag for the host
+        for (int q = 0; q < NQ; ++q) out[(long long)q * ncells + i] = __builtin_nan("");
+        atomicOr(flags, FLAG_BAD_CELL);
+        return;
+    }
     int x = n % bx.nx, y = (n / bx.nx) % bx.ny, z = n / ((long long)bx.nx * bx.ny);
     const typename S::T* g = (const typename S::T*)bx.grid[parity];
 #pragma unroll
@@ -1157,12 +1167,14 @@ __global__ __launch_bounds__(256) void k_integrate(IntParams ip) {
     if (SCHEME == SCHEME_VERLET) ip.P.prev_ok[p] = 1;
 }
 
-__global__ void k_check_lists(const int* __restrict__ stats, long long cap, int* __restrict__ err) {
+// Replace the list bits of the error word by those of the lists just built
+// (report = 0: clear them only, for a build whose counts the host checks).
+__global__ void k_check_lists(const int* __restrict__ stats, long long cap, int* __restrict__ err, int report) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         int e = 0;
-        if ((long long)stats[1] > cap) e |= 1;
-        if (stats[0] > MAXC) e |= 2;
-        if (e) err[0] |= e;
+        if ((long long)stats[1] > cap) e |= FLAG_LIST_ENTRIES;
+        if (stats[0] > MAXC) e |= FLAG_LIST_TILE;
+        err[0] = (err[0] & ~(FLAG_LIST_ENTRIES | FLAG_LIST_TILE)) | (report ? e : 0);
     }
 }
 
@@ -1262,12 +1274,12 @@ hipError_t launch_get_pdfs(int storage, const BoxDev& bx, int parity, double* f,
 }
 
 hipError_t launch_get_pdfs_at(int storage, const BoxDev& bx, int parity, const int* cells, int ncells, double* out,
-                              float inv, hipStream_t st) {
+                              float inv, int* flags, hipStream_t st) {
     unsigned g = blocks_for(ncells, 256);
     switch (storage) {
-        case 0: hipLaunchKernelGGL(k_get_pdfs_at<St64>, dim3(g), dim3(256), 0, st, bx, parity, cells, ncells, out, inv); break;
-        case 1: hipLaunchKernelGGL(k_get_pdfs_at<St32>, dim3(g), dim3(256), 0, st, bx, parity, cells, ncells, out, inv); break;
-        default: hipLaunchKernelGGL(k_get_pdfs_at<St16>, dim3(g), dim3(256), 0, st, bx, parity, cells, ncells, out, inv); break;
+        case 0: hipLaunchKernelGGL(k_get_pdfs_at<St64>, dim3(g), dim3(256), 0, st, bx, parity, cells, ncells, out, inv, flags); break;
+        case 1: hipLaunchKernelGGL(k_get_pdfs_at<St32>, dim3(g), dim3(256), 0, st, bx, parity, cells, ncells, out, inv, flags); break;
+        default: hipLaunchKernelGGL(k_get_pdfs_at<St16>, dim3(g), dim3(256), 0, st, bx, parity, cells, ncells, out, inv, flags); break;
     }
     return hipGetLastError();
 }
@@ -1313,8 +1325,8 @@ hipError_t launch_integrate(int scheme, const IntParams& ip, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_check_lists(const int* stats, long long cap, int* err, hipStream_t st) {
-    hipLaunchKernelGGL(k_check_lists, dim3(1), dim3(64), 0, st, stats, cap, err);
+hipError_t launch_check_lists(const int* stats, long long cap, int* err, int report, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_lists, dim3(1), dim3(64), 0, st, stats, cap, err, report);
     return hipGetLastError();
 }
 

@@ -83,6 +83,8 @@ def test_null_context_calls():
     assert L.psm_set_dynamics(None, 0, 1.0, None) == psm.PSM_EINVAL
     assert L.psm_get_particles(None, 0, None, None, None) == psm.PSM_EINVAL
     assert L.psm_set_launch(None, 64, 4, 1, 0) == psm.PSM_EINVAL
+    assert L.psm_set_drift_check(None, 0, 1e-12) == psm.PSM_EINVAL
+    assert L.psm_set_strict_slots(None, 1) == psm.PSM_EINVAL
     assert "NULL" in psm.psm_last_error() or "ctx" in psm.psm_last_error()
 
 
@@ -172,3 +174,15 @@ def test_last_error_is_per_thread():
         t.join()
     for key, msgs in seen.items():
         assert len(msgs) == 200 and all(key in m for m in msgs), (key, set(msgs))
+
+
+def test_plane_size_limit():
+    """In-plane byte offsets are 32-bit signed: a z-plane (rows padded to whole
+    64-cell blocks, 19 FP64 values per cell, plus one block) must stay below
+    2^31 bytes. 4096 x 3449 cells fit, 4096 x 3450 do not."""
+    ok = psm.make_desc(4096, 3449, 4, 0.6)
+    assert 4096 * 3449 * 19 * 8 + 64 * 19 * 8 < 2 ** 31 <= 4096 * 3450 * 19 * 8 + 64 * 19 * 8
+    assert psm.psm_workspace_size([ok], psm.PSM_FP16DEV) > 0
+    with pytest.raises(psm.PsmError) as e:
+        psm.psm_workspace_size([psm.make_desc(4096, 3450, 4, 0.6)], psm.PSM_FP16DEV)
+    assert e.value.code == psm.PSM_EINVAL and "2^31" in str(e.value)

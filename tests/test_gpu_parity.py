@@ -182,8 +182,11 @@ def test_stats_mass_and_momentum():
 
 
 def test_tile_capacity_error_is_reported():
-    """More sphere candidates in one tile than the kernel stages is refused
-    with PSM_ECAPACITY, and the context keeps working."""
+    """More sphere candidates in one tile than the kernel stages: the lists
+    are built on the device without waiting, the list of that tile is cut (a
+    step still runs in bounds), the next synchronising call reports
+    PSM_ECAPACITY, the context refuses to step, and a valid set makes it
+    usable again."""
     dims = (64, 64, 64)
     rng = np.random.default_rng(5)
     n = 80
@@ -192,11 +195,20 @@ def test_tile_capacity_error_is_reported():
     eng = psm.Engine([psm.make_desc(*dims, 0.7, max_particles=n, max_radius=2.0)])
     eng.set_equilibrium(0, np.zeros((3, dims[0] * dims[1] * dims[2])))
     eng.set_launch(256, 1, 32)
-    with pytest.raises(psm.PsmError) as e:
-        eng.set_particles(0, x, r, np.zeros((n, 3)))
-    assert e.value.code == psm.PSM_ECAPACITY
-    eng.set_particles(0, x[:4], r[:4], np.zeros((4, 3)))
+    eng.set_particles(0, x, r, np.zeros((n, 3)))
     eng.step(1)
+    with pytest.raises(psm.PsmError) as e:
+        eng.get_forces(0)
+    assert e.value.code == psm.PSM_ECAPACITY
+    with pytest.raises(psm.PsmError) as e:
+        eng.step(1)
+    assert e.value.code == psm.PSM_ESTATE
+    eng.set_particles(0, x[:4], r[:4], np.zeros((4, 3)))
+    eng.set_equilibrium(0, np.zeros((3, dims[0] * dims[1] * dims[2])))
+    eng.step(1)
+    F, _ = eng.get_forces(0)
+    assert np.all(np.isfinite(F))
+    eng.close()
 
 
 def test_velocity_only_update_keeps_lists_and_uses_new_velocities():

@@ -135,73 +135,115 @@ def stream_copy_gbps(psm, torch, nbytes=4 << 30, reps=20):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def precision_errors(psm, torch, inputs, n=64, steps=1000):
-    """L2 velocity error and max relative force error of the deviation
-    storage forms against the FP64 path on an n^3 copy of the workload."""
+PRECISION_COPY = (64, 1000)   # edge and steps of the precision copy of the workload
+
+
+def velocity_error(u, u_ref):
+    """L2 of u - u_ref over all cells relative to the L2 of u_ref."""
     import numpy as np
 
+    return float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))
+
+
+def force_error(F, F_ref, A=None):
+    """max_p |dF_p| / max(|F_p|, 0.01 A_p), A_p the sum of the terms' magnitudes
+    B |g| over the sphere's cells (no floor when A is not known)."""
+    import numpy as np
+
+    d = np.linalg.norm(F - F_ref, axis=1)
+    den = np.linalg.norm(F_ref, axis=1)
+    if A is not None:
+        den = np.maximum(den, 0.01 * A)
+    return float(np.max(d / den))
+
+
+def precision_copy_runs(psm, torch, inputs):
+    """The three storage forms on the 64^3 copy of the workload for 1000
+    steps: velocity field and forces of each (the errors against the oracle
+    are taken in the CPU-baseline leg, which runs the oracle on the same copy),
+    and the deviation forms' errors against the GPU FP64 path."""
+    import numpy as np
+
+    n, steps = PRECISION_COPY
     spec = inputs.paper_scale(n=n, seed=1)
-    out = {}
-    ref = None
+    runs = {}
     for st in (0, 1, 2):
         eng = psm.Engine([psm.desc_from_spec(spec)], storage=st)
         eng.set_equilibrium(0, np.zeros((3, spec.N)))
         eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+        eng.set_graph(True)
         eng.step(steps)
         _, u = eng.get_macroscopic(0)
         F, _ = eng.get_forces(0)
-        u = u.cpu().numpy()
+        runs[st] = (u.cpu().numpy(), F)
         eng.close()
-        if st == 0:
-            ref = (u, F)
-            continue
-        l2 = float(np.linalg.norm(u - ref[0]) / np.linalg.norm(ref[0]))
-        fe = float(np.max(np.linalg.norm(F - ref[1], axis=1) / np.linalg.norm(ref[1], axis=1)))
-        out[STORAGE_NAME[st]] = {"l2_u_rel": l2, "max_force_rel": fe}
-    return out
+    errs = {}
+    for st in (1, 2):
+        errs[STORAGE_NAME[st]] = {"l2_u_rel": velocity_error(runs[st][0], runs[0][0]),
+                                  "force_rel": force_error(runs[st][1], runs[0][1])}
+    return runs, errs
 
 
 def run_batched(psm, torch, inputs, steps=500, nbox=64):
-    """64 independent uneven boxes in one launch per step, FP32 deviation
-    storage, replayed as captured 10-step HIP graphs, at the autotuner's
-    launch and at the same tile shape on the persistent grid (an
-    occupancy-sized grid whose workgroups walk the tiles of all boxes)."""
+    """64 independent uneven boxes in one launch per step, replayed as
+    captured 10-step HIP graphs at the autotuner's launch: FP32 deviation
+    storage (the batched form), the same boxes in FP64 storage for its
+    speed-up and velocity error, and the FP32 boxes once more on the
+    persistent grid (an occupancy-sized grid whose workgroups walk the tiles
+    of all boxes) at the same tile shape."""
     import numpy as np
 
     specs = inputs.batched_boxes(nbox=nbox, seed=3)
     descs = [psm.desc_from_spec(s, max_particles=max(s.n_particles, 1), max_radius=8.0) for s in specs]
-    eng = psm.Engine(descs, storage=psm.PSM_FP32DEV)
-    for b, s in enumerate(specs):
-        if s.n_particles:
-            eng.set_particles(b, s.x, s.r, s.U, s.Om)
-    for b, s in enumerate(specs):
-        eng.set_equilibrium(b, s.u0)
-    shape, _ = eng.autotune(trial_steps=10)
-    for b, s in enumerate(specs):
-        eng.set_equilibrium(b, s.u0)
-    eng.set_graph(True)
-
-    def timed():
-        eng.step(20)
-        eng.synchronize()
-        t0 = time.perf_counter()
-        eng.step(steps)
-        eng.synchronize()
-        return time.perf_counter() - t0
-
-    dt = timed()
     cells = sum(s.N for s in specs)
-    mass_ok = all(np.isfinite(eng.get_stats(b)[0]) for b in range(len(specs)))
-    pshape = (shape[0], shape[1], shape[2], shape[3] | psm.PSM_LAUNCH_PERSISTENT)
-    eng.set_launch(*pshape)
-    dtp = timed()
-    eng.close()
-    torch.cuda.empty_cache()
+
+    def run(storage, persistent_too=False):
+        eng = psm.Engine(descs, storage=storage)
+        for b, s in enumerate(specs):
+            if s.n_particles:
+                eng.set_particles(b, s.x, s.r, s.U, s.Om)
+        for b, s in enumerate(specs):
+            eng.set_equilibrium(b, s.u0)
+        shape, _ = eng.autotune(trial_steps=10)
+
+        def timed():
+            for b, s in enumerate(specs):
+                eng.set_equilibrium(b, s.u0)
+            eng.set_graph(True)
+            eng.step(20)
+            eng.synchronize()
+            t0 = time.perf_counter()
+            eng.step(steps)
+            eng.synchronize()
+            return time.perf_counter() - t0
+
+        dt = timed()
+        u = [eng.get_macroscopic(b)[1].cpu().numpy() for b in range(len(specs))]
+        finite = all(np.isfinite(eng.get_stats(b)[0]) for b in range(len(specs)))
+        res = {"dt": dt, "u": u, "shape": shape, "finite": finite}
+        if persistent_too:
+            pshape = (shape[0], shape[1], shape[2], shape[3] | psm.PSM_LAUNCH_PERSISTENT)
+            eng.set_launch(*pshape)
+            res["pshape"], res["dtp"] = pshape, timed()
+        eng.close()
+        torch.cuda.empty_cache()
+        return res
+
+    r32 = run(psm.PSM_FP32DEV, persistent_too=True)
+    r64 = run(psm.PSM_FP64)
+    num = sum(float(np.sum((a - b) ** 2)) for a, b in zip(r32["u"], r64["u"]))
+    den = sum(float(np.sum(b ** 2)) for b in r64["u"])
+    dt = r32["dt"]
     return {"boxes": len(specs), "cells": cells, "spheres": int(sum(s.n_particles for s in specs)),
             "steps": steps, "mlups": cells * steps / dt / 1e6, "ms_per_step": dt * 1e3 / steps,
-            "storage": "f32dev", "launch": list(shape), "graph_steps": 10, "finite": bool(mass_ok),
+            "storage": "f32dev", "launch": list(r32["shape"]), "graph_steps": 10, "finite": bool(r32["finite"]),
             "roofline_frac": cells * 152 / (dt / steps) / 1e9 / HBM_PEAK_GBPS,
-            "persistent_launch": list(pshape), "mlups_persistent": cells * steps / dtp / 1e6}
+            "f64_mlups": cells * steps / r64["dt"] / 1e6, "f64_launch": list(r64["shape"]),
+            "speedup_vs_f64": r64["dt"] / dt,
+            "l2_u_rel_vs_f64": (num / den) ** 0.5,
+            "persistent_launch": list(r32["pshape"]), "mlups_persistent": cells * steps / r32["dtp"] / 1e6,
+            "launch_form": "one workgroup per tile over the tiles of all boxes (mlups); the persistent grid is "
+                           "reported beside it (mlups_persistent)"}
 
 
 def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=False):
@@ -226,14 +268,38 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
     inertia = 0.4 * mass * spec.r ** 2
     L = np.asarray(spec.dims, dtype=np.float64)
 
-    def one():
+    # per-module record of the host-driven loop: host times around each call,
+    # and events on the engine's stream around the upload + re-binning and
+    # the step launches
+    rec = {"set_particles": 0.0, "step_call": 0.0, "get_forces": 0.0, "euler": 0.0}
+    evs = []
+
+    def one(record=False):
         nonlocal x, U, Om
+        if record:
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(eng.stream)
+        t0 = time.perf_counter()
         eng.set_particles(0, x, spec.r, U, Om)
+        t1 = time.perf_counter()
+        if record:
+            e[1].record(eng.stream)
         eng.step(1)
+        if record:
+            e[2].record(eng.stream)
+        t2 = time.perf_counter()
         F, T = eng.get_forces(0)
+        t3 = time.perf_counter()
         x = np.mod(x + U, L)
         U = U + F / mass[:, None]
         Om = Om + T / inertia[:, None]
+        t4 = time.perf_counter()
+        if record:
+            evs.append(e)
+            rec["set_particles"] += t1 - t0
+            rec["step_call"] += t2 - t1
+            rec["get_forces"] += t3 - t2
+            rec["euler"] += t4 - t3
 
     if device:
         # kernel time from an eager timed pass, wall time from graph replays
@@ -260,9 +326,30 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
         eng.set_timing(True)
         t0 = time.perf_counter()
         for _ in range(steps):
-            one()
+            one(record=True)
         dt = time.perf_counter() - t0
         nl, kms = eng.get_timing()
+        eng.set_timing(False)
+        up = sum(a.elapsed_time(b) for a, b, _ in evs) / steps
+        launches = sum(b.elapsed_time(c) for _, b, c in evs) / steps
+        # the read-back alone: D2H of the forces and the synchronisation on an idle stream
+        eng.synchronize()
+        t0r = time.perf_counter()
+        for _ in range(20):
+            eng.get_forces(0)
+        d2h = (time.perf_counter() - t0r) * 1e3 / 20
+        kern_ms = kms / max(nl, 1)
+        breakdown = {
+            "host_set_particles_ms": rec["set_particles"] * 1e3 / steps,
+            "host_euler_ms": rec["euler"] * 1e3 / steps,
+            "gpu_upload_and_binning_ms": up,
+            "gpu_step_kernel_ms": kern_ms,
+            "gpu_force_reduction_and_gaps_ms": launches - kern_ms,
+            "readback_d2h_sync_ms": d2h,
+            "wall_ms": dt * 1e3 / steps,
+            "note": "host times measured around each call (set_particles enqueues the upload and the device "
+                    "re-binning without waiting); GPU times from events on the engine stream",
+        }
     _, _, ov = eng.get_stats(0)
     kern0 = kernel_ms_without_spheres(eng) if device else None
     eng.close()
@@ -270,6 +357,8 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
     step_ms = dt * 1e3 / steps
     kern = kms / max(nl, 1)
     extra = {} if kern0 is None else {"kernel_ms_no_spheres": kern0, "kernel_over_no_spheres": kern / kern0 - 1.0}
+    if not device:
+        extra["breakdown"] = breakdown
     return {"cells": spec.N, "spheres": int(len(spec.r)), "steps": steps, "storage": "f32dev",
             "mlups": spec.N * steps / dt / 1e6, "ms_per_step": step_ms, "kernel_ms": kern, **extra,
             "coupling_overhead_frac": (step_ms - kern) / step_ms, "launch": list(shape),
@@ -342,21 +431,71 @@ def kernel_ms_without_spheres(eng, steps=30):
     return kms / max(nl, 1)
 
 
-def cpu_baseline(inputs, n, steps):
+def host_cpu():
+    """CPU model and the number of cores this process may use."""
+    model, fam, mod = "unknown", "?", "?"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and model == "unknown":
+                    model = v
+                elif k == "cpu family" and fam == "?":
+                    fam = v
+                elif k == "model" and mod == "?":
+                    mod = v
+    except OSError:
+        pass
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return f"{model} (family {fam}, model {mod})", cores
+
+
+def cpu_baseline(inputs, n, steps, copy_runs=None):
+    """The FP64 C oracle as written on the host's cores: single-threaded (the
+    build every test uses) and on all cores (the OpenMP timing build of the
+    same source) on an n^3 sample of the workload for `steps` steps; then,
+    on all cores, the oracle on the 64^3 precision copy (1000 steps), which is
+    the reference of the deviation forms' errors in `copy_runs`."""
     import numpy as np
     import oracle
 
     oracle.build(force=False)
+    model, cores = host_cpu()
     spec = inputs.paper_scale(n=n, seed=1)
     box = oracle.Box(*spec.dims, tau=spec.tau, fext=spec.fext)
     f0 = oracle.equilibrium(box, np.zeros((3, spec.N)))
     t0 = time.perf_counter()
     oracle.run(box, f0, steps, spec.x, spec.r, spec.U, spec.Om)
-    dt = time.perf_counter() - t0
-    return {"value": spec.N * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{n}^3 periodic box with the same sphere size, solid fraction (0.10, "
-                      f"{len(spec.r)} spheres), tau and body force, {steps} FP64 steps, "
-                      f"single-threaded C oracle, {dt:.1f} s"}
+    dt1 = time.perf_counter() - t0
+    log(f"  1 thread: {spec.N * steps / dt1 / 1e6:.2f} MLUPS ({dt1:.1f} s)")
+    nth = oracle.threads(cores)
+    t0 = time.perf_counter()
+    oracle.run(box, f0, steps, spec.x, spec.r, spec.U, spec.Om, timing_build=True)
+    dtn = time.perf_counter() - t0
+    log(f"  {nth} threads: {spec.N * steps / dtn / 1e6:.2f} MLUPS ({dtn:.1f} s)")
+    del f0
+    out = {"value": spec.N * steps / dtn / 1e6, "unit": "MLUPS", "cores": nth, "kind": "oracle",
+           "sample": f"{n}^3 periodic box with the workload's sphere size, solid fraction (0.10, {len(spec.r)} "
+                     f"spheres), tau and body force, {steps} FP64 steps; all-core figure from the OpenMP build of "
+                     f"the C oracle ({dtn:.1f} s), single-thread figure from the plain build ({dt1:.1f} s)",
+           "single_thread": {"value": spec.N * steps / dt1 / 1e6, "cores": 1},
+           "host_cpu": model, "host_cores": cores}
+    if copy_runs is not None:
+        cn, csteps = PRECISION_COPY
+        cs = inputs.paper_scale(n=cn, seed=1)
+        cbox = oracle.Box(*cs.dims, tau=cs.tau, fext=cs.fext)
+        t0 = time.perf_counter()
+        ref = oracle.run(cbox, oracle.equilibrium(cbox, np.zeros((3, cs.N))), csteps, cs.x, cs.r, cs.U, cs.Om,
+                         timing_build=True)
+        dtc = time.perf_counter() - t0
+        _, u_ref = oracle.macroscopic(cbox, ref.f)
+        errs = {}
+        for st, (u, F) in copy_runs.items():
+            errs[STORAGE_NAME[st]] = {"l2_u_rel": velocity_error(u, u_ref), "force_rel": force_error(F, ref.F, ref.A)}
+        out["precision_copy_oracle"] = {"value": cs.N * csteps / dtc / 1e6, "cores": nth, "seconds": dtc}
+        out["_errors_vs_oracle"] = errs
+    return out
 
 
 def main():
@@ -367,16 +506,18 @@ def main():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--launch", type=str, default=None, help="tx,ty,tz,flags (skips the autotuner)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--retune", action="store_true",
+                    help="autotune the main run even where a committed counter run fixes its launch")
     ap.add_argument("--kernel-only", action="store_true", help="time psm_step alone (no upload/readback)")
     ap.add_argument("--storage", choices=list(STORAGE_OF), default="f64",
                     help="storage form of the main run (another than f64 skips the precision-form runs)")
-    ap.add_argument("--precision-steps", type=int, default=200)
+    ap.add_argument("--precision-steps", type=int, default=None, help="steps of the FP32/FP16 runs (default --steps)")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-size", type=int, default=128)
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--cpu-size", type=int, default=256)
+    ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--batched-steps", type=int, default=500)
-    ap.add_argument("--dense-steps", type=int, default=200)
+    ap.add_argument("--dense-steps", type=int, default=500)
     ap.add_argument("--dense-size", type=int, default=768)
     ap.add_argument("--bed-steps", type=int, default=200)
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and dense workloads")
@@ -398,34 +539,51 @@ def main():
     psm.lib()
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
 
+    def counter_launch(st):
+        """The launch of the committed counter run of this storage form (chosen
+        by the autotuner in that run), so that the timed launch is the one the
+        HBM traffic was counted at; None if the counters are stale."""
+        if args.launch or args.retune or args.no_autotune or args.size != 512:
+            return None
+        _, cl = measured_traffic(st)
+        return tuple(cl) if cl else None
+
     spec = inputs.paper_scale(n=args.size, seed=1)
     log(f"workload: {args.size}^3, {len(spec.r)} spheres, tau {spec.tau}, g {spec.fext[0]}")
 
     main_st = STORAGE_OF[args.storage]
-    log(f"{args.storage} main run")
-    main_res = run_case(psm, torch, spec, main_st, args.steps, args.warmup, not args.no_autotune, launch,
+    main_launch = launch or counter_launch(main_st)
+    log(f"{args.storage} main run" + (f" at the counter run's launch {main_launch}" if main_launch and not launch else ""))
+    main_res = run_case(psm, torch, spec, main_st, args.steps, args.warmup, not args.no_autotune, main_launch,
                         full_loop=not args.kernel_only)
     log(f"  {main_res}")
 
+    def traffic_at(st, used_launch):
+        traffic, tl = measured_traffic(st)
+        return (traffic, tl) if tl is not None and list(tl) == list(used_launch) else (None, tl)
+
     forms = {}
+    copy_runs = None
     if not args.no_precision and main_st == 0:
+        psteps = args.precision_steps or args.steps
         for st in (1, 2):
             log(f"{STORAGE_NAME[st]} run")
-            r = run_case(psm, torch, spec, st, args.precision_steps, 10, not args.no_autotune, None,
+            r = run_case(psm, torch, spec, st, psteps, args.warmup, not args.no_autotune, counter_launch(st),
                          full_loop=not args.kernel_only)
             r["roofline_frac"] = spec.N * BYTES_PER_CELL[st] / (r["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS
-            traffic, traffic_launch = measured_traffic(st)
-            forms[STORAGE_NAME[st]] = {"mlups": r["mlups"], "ms_per_step": r["ms_per_step"],
+            traffic, traffic_launch = traffic_at(st, r["launch"])
+            forms[STORAGE_NAME[st]] = {"mlups": r["mlups"], "ms_per_step": r["ms_per_step"], "steps": psteps,
                                        "kernel_ms": r["kernel_ms"], "launch": r["launch"],
                                        "roofline_frac": r["roofline_frac"],
                                        "traffic": traffic, "traffic_launch": traffic_launch,
-                                       "speedup_vs_f64": r["mlups"] / main_res["mlups"]}
+                                       "speedup_vs_f64": r["mlups"] / main_res["mlups"],
+                                       "kernel_speedup_vs_f64": main_res["kernel_ms"] / r["kernel_ms"]}
             log(f"  {forms[STORAGE_NAME[st]]}")
-        log("precision errors (64^3 copy, 1000 steps, vs the FP64 path)")
-        err = precision_errors(psm, torch, inputs)
+        log("precision copy (64^3, 1000 steps) in the three storage forms")
+        copy_runs, err = precision_copy_runs(psm, torch, inputs)
         for k, v in err.items():
-            forms[k]["error_vs_f64_64cubed_1000steps"] = v
-        log(f"  {err}")
+            forms[k]["error_vs_gpu_f64_64cubed_1000steps"] = v
+        log(f"  vs the GPU FP64 path: {err}")
 
     extra = {}
     if not args.no_extra:
@@ -451,8 +609,15 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(inputs, args.cpu_size, args.cpu_steps)
+        cpu = cpu_baseline(inputs, args.cpu_size, args.cpu_steps, copy_runs)
+        errs = cpu.pop("_errors_vs_oracle", {})
+        for k, v in errs.items():
+            if k in forms:
+                forms[k]["error_vs_oracle_64cubed_1000steps"] = v
+            elif k == "f64":
+                forms["f64_error_vs_oracle_64cubed_1000steps"] = v
         log(f"  {cpu}")
+        log(f"  errors vs the oracle: {errs}")
 
     for case in ("dilute", "dense"):
         bed = extra.get(f"fluidized_bed_{case}")
@@ -464,7 +629,7 @@ def main():
 
     algo_bytes = spec.N * BYTES_PER_CELL[main_st]
     achieved = algo_bytes / (main_res["kernel_ms"] * 1e-3) / 1e9
-    traffic, traffic_launch = measured_traffic(main_st)
+    traffic, traffic_launch = traffic_at(main_st, main_res["launch"])
     form = {0: "FP64", 1: "FP32-deviation storage", 2: "FP16-deviation storage"}[main_st]
     out = {
         "metric": METRIC,

@@ -3,12 +3,25 @@
 FP32 stores d = f - w_q, FP16 stores 2^10 d; both collide in FP32 and keep
 forces, torques and mass sums in FP64. Their error against the oracle is a
 property of the rounding, not a parity bar; the bounds asserted here are the
-stated error bounds of these forms (measured values are a few times lower):
-after 100 steps of a 32^3 Taylor-Green box with 4 spheres (r = 4, linear
-mapping, tau 0.6):
-  FP32-dev: L2 relative velocity error <= 2e-5, max relative force error <= 1e-4
-  FP16-dev: L2 relative velocity error <= 3e-3, max relative force error <= 2e-2
+stated error bounds of these forms (about three times the measured values).
+
+Velocity error: L2 of u over all cells relative to the L2 of the oracle's u.
+Force error: max over spheres of |dF_p| / max(|F_p|, 0.01 A_p), A_p the sum
+over the sphere's cells of B |g| (the magnitude of the terms of eq. 21): a
+sphere whose force nearly cancels is measured against 1 % of its terms.
+
+(a) The precision copy of the 512^3 workload: 64^3 periodic box, tau 0.55,
+body force 1e-6 along +x, fluid at rest, 6 spheres of radius 10 (10 % solid,
+seed 1) with velocities in [-0.005, 0.005]^3, linear mapping, 1000 steps:
+  FP32-dev: L2 velocity error <= 5e-5, force error <= 4e-4
+  FP16-dev: L2 velocity error <= 6e-4, force error <= 7e-3
+(b) 100 steps of a 32^3 Taylor-Green box with 4 spheres (r = 4, tau 0.6):
+  FP32-dev: L2 velocity error <= 2e-5, force error <= 1e-4
+  FP16-dev: L2 velocity error <= 3e-3, force error <= 2e-2
 """
+import os
+import time
+
 import numpy as np
 import pytest
 
@@ -20,6 +33,49 @@ from psm_cases import initial_f, make_engine, run_oracle
 pytestmark = pytest.mark.gpu
 
 BOUNDS = {psm.PSM_FP32DEV: (2e-5, 1e-4), psm.PSM_FP16DEV: (3e-3, 2e-2)}
+BOUNDS_COPY = {psm.PSM_FP32DEV: (5e-5, 4e-4), psm.PSM_FP16DEV: (6e-4, 7e-3)}
+
+
+def force_error(F, F_ref, A):
+    """max_p |dF_p| / max(|F_p|, 0.01 A_p)."""
+    d = np.linalg.norm(F - F_ref, axis=1)
+    return float(np.max(d / np.maximum(np.linalg.norm(F_ref, axis=1), 0.01 * A)))
+
+
+@pytest.fixture(scope="module")
+def copy_reference():
+    """The oracle on the 64^3 precision copy, 1000 steps. It runs the OpenMP
+    timing build of the oracle (the same arithmetic per cell; only the order
+    of the force sums over cells differs, far below these bounds)."""
+    spec = inputs.paper_scale(n=64, seed=1)
+    box = oracle.Box(*spec.dims, tau=spec.tau, fext=spec.fext)
+    f0 = oracle.equilibrium(box, np.zeros((3, spec.N)))
+    oracle.threads(min(16, os.cpu_count() or 1))
+    print(f"[precision copy] oracle 64^3 x 1000 steps, {len(spec.r)} spheres ...", flush=True)
+    t0 = time.perf_counter()
+    ref = oracle.run(box, f0, 1000, spec.x, spec.r, spec.U, spec.Om, timing_build=True)
+    print(f"[precision copy] oracle done in {time.perf_counter() - t0:.1f} s", flush=True)
+    _, u_ref = oracle.macroscopic(box, ref.f)
+    return spec, u_ref, ref
+
+
+@pytest.mark.parametrize("storage", [psm.PSM_FP32DEV, psm.PSM_FP16DEV])
+def test_precision_copy_of_the_paper_scale_workload(storage, copy_reference):
+    spec, u_ref, ref = copy_reference
+    eng = make_engine([spec], storage=storage)
+    eng.set_equilibrium(0, np.zeros((3, spec.N)))
+    eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+    eng.set_graph(True)
+    eng.step(1000)
+    _, u = eng.get_macroscopic(0)
+    F, _ = eng.get_forces(0)
+    eng.close()
+    u = u.cpu().numpy()
+    l2 = float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))
+    fe = force_error(F, ref.F, ref.A)
+    print(f"[precision copy] storage {storage}: L2 u {l2:.3e}, force {fe:.3e}", flush=True)
+    bu, bf = BOUNDS_COPY[storage]
+    assert l2 <= bu and fe <= bf
 
 
 def _spec():
@@ -46,8 +102,8 @@ def test_deviation_storage_error_bounds(storage):
     F, T = eng.get_forces(0)
     u = u.cpu().numpy()
     l2 = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
-    fe = np.max(np.linalg.norm(F - ref.F, axis=1) / np.linalg.norm(ref.F, axis=1))
-    print(f"[precision] storage {storage}: L2 u {l2:.3e}, max rel force {fe:.3e}", flush=True)
+    fe = force_error(F, ref.F, ref.A)
+    print(f"[precision] storage {storage}: L2 u {l2:.3e}, force {fe:.3e}", flush=True)
     bu, bf = BOUNDS[storage]
     assert l2 <= bu and fe <= bf
     # FP64 mass bookkeeping of the rounded state stays close to the true mass
@@ -98,8 +154,8 @@ def test_fp16_scale_choice(scale):
     F, T = eng.get_forces(0)
     u = u.cpu().numpy()
     l2 = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
-    fe = np.max(np.linalg.norm(F - ref.F, axis=1) / np.linalg.norm(ref.F, axis=1))
-    print(f"[precision] FP16 scale {scale:g}: L2 u {l2:.3e}, max rel force {fe:.3e}", flush=True)
+    fe = force_error(F, ref.F, ref.A)
+    print(f"[precision] FP16 scale {scale:g}: L2 u {l2:.3e}, force {fe:.3e}", flush=True)
     bu, bf = BOUNDS[psm.PSM_FP16DEV]
     assert l2 <= bu and fe <= bf
     eng.close()

@@ -270,6 +270,19 @@ int psm_set_timing(psm_ctx* ctx, int enable);
 int psm_get_timing(psm_ctx* ctx, long long* launches, double* total_ms);
 int psm_reset_timing(psm_ctx* ctx);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the mass and
+ * momentum totals of psm_get_stats for a canonical FP64 field f (device
+ * [19][ncells], the layout of psm_get_pdfs), without a context: out (device
+ * double[4]) receives sum_x sum_q f, then sum_x sum_q f c_q (x, y, z).
+ * Asynchronous on hip_stream, which must belong to the current device; it
+ * calls no allocating routine. Its partial sums live in a library-owned
+ * static device array of 128 KiB per GPU (kept until the process ends), so
+ * ncells is at most 67,108,864 (PSM_EINVAL beyond); ncells = 0 gives zeros.
+ * Calls that overlap on one GPU (different streams) race on that array. The
+ * first call on a device looks the array up; make it outside stream capture. */
+int psm_field_stats_noalloc(const double* f, long long ncells, double* out, void* hip_stream);
+
 /* Bandwidth reference (the paper's SCALE/STREAM measurement, Sec. 4): copy
  * `bytes` (multiple of 16, at most 2^31 * 4 KiB) from src to dst (device,
  * 16-byte aligned, not overlapping) on hip_stream with a plain one-shot

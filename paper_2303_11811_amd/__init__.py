@@ -78,6 +78,7 @@ _SIGS = {
     "psm_get_particles": ([_P, ctypes.c_int, _D, _D, _D], ctypes.c_int),
     "psm_run": ([_P, ctypes.c_int, ctypes.c_double, ctypes.c_int], ctypes.c_int),
     "psm_stream_copy": ([_P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "psm_field_stats_noalloc": ([_P, ctypes.c_longlong, _P, _P], ctypes.c_int),
     "psm_last_error": ([], ctypes.c_char_p),
 }
 
@@ -276,6 +277,10 @@ def psm_get_timing(ctx):
 
 def psm_reset_timing(ctx):
     return _check(lib().psm_reset_timing(ctx))
+
+
+def psm_field_stats_noalloc(f_ptr, ncells, out_ptr, stream):
+    return _check(lib().psm_field_stats_noalloc(_P(f_ptr), ctypes.c_longlong(ncells), _P(out_ptr), _P(stream)))
 
 
 def psm_stream_copy(src_ptr, dst_ptr, nbytes, stream):

@@ -1176,6 +1176,16 @@ extern "C" int psm_autotune(psm_ctx* c, int trial_steps, int* tx, int* ty, int* 
     return PSM_OK;
 }
 
+extern "C" int psm_field_stats_noalloc(const double* f, long long ncells, double* out, void* hip_stream) {
+    if (ncells < 0) return fail(PSM_EINVAL, "ncells < 0");
+    if (ncells > noalloc_max_cells())
+        return fail(PSM_EINVAL, "psm_field_stats_noalloc: %lld cells, at most %lld (fixed scratch)", ncells,
+                    noalloc_max_cells());
+    if ((ncells > 0 && !f) || !out) return fail(PSM_EINVAL, "f/out is NULL");
+    HIP_TRY(launch_field_stats_noalloc(f, ncells, out, (hipStream_t)hip_stream));
+    return PSM_OK;
+}
+
 extern "C" int psm_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream) {
     if (!src || !dst) return fail(PSM_EINVAL, "NULL pointer");
     if (bytes % 16) return fail(PSM_EINVAL, "bytes must be a multiple of 16");

@@ -323,5 +323,9 @@ enum {
 // 0: clear the list bits only)
 hipError_t launch_check_lists(const int* stats, long long cap, int* err, int report, hipStream_t st);
 hipError_t launch_fill_int(int* a, long long n, int v, hipStream_t st);
+// FP64 mass and momentum of a canonical field [19][N] into out[4] (device),
+// with the partial sums in the library's static per-GPU array
+long long noalloc_max_cells();
+hipError_t launch_field_stats_noalloc(const double* f, long long N, double* out, hipStream_t st);
 
 }  // namespace psm

@@ -16,6 +16,8 @@
 // and sums the per-sphere force/torque of its tile deterministically.
 #include "psm_internal.h"
 
+#include <mutex>
+
 namespace psm {
 
 #define GLOBAL __attribute__((address_space(1)))
@@ -1176,6 +1178,78 @@ __global__ void k_check_lists(const int* __restrict__ stats, long long cap, int*
         if (stats[0] > MAXC) e |= FLAG_LIST_TILE;
         err[0] = (err[0] & ~(FLAG_LIST_ENTRIES | FLAG_LIST_TILE)) | (report ? e : 0);
     }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 totals of a canonical field without a context or a workspace, for
+// callers that cannot allocate device memory. The per-block partial sums go
+// to a library-owned array (one copy per GPU, alive until the process ends):
+// block b sums cells [b * NOALLOC_CELLS_PER_BLOCK, (b + 1) * ...), each
+// thread 64 cells 256 apart in cell order, then a fixed tree in LDS; one
+// more kernel adds the blocks in order. Every partial slot a call reads was
+// written by the same call, so nothing needs clearing; calls that overlap on
+// one GPU (different streams) race on the array.
+constexpr int NOALLOC_BLOCKS = 4096;
+constexpr long long NOALLOC_CELLS_PER_BLOCK = 256LL * 64;
+static __device__ __align__(256) double scratch[NOALLOC_BLOCKS * 4];
+
+__global__ __launch_bounds__(256) void k_field_stats_partial(const double* __restrict__ f, long long N,
+                                                             double* __restrict__ part) {
+    __shared__ double s[4][256];
+    double m = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+    const long long c0 = (long long)blockIdx.x * NOALLOC_CELLS_PER_BLOCK + threadIdx.x;
+    for (int k = 0; k < 64; ++k) {
+        const long long n = c0 + 256LL * k;
+        if (n >= N) break;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const double v = f[(long long)q * N + n];
+            m += v;
+            px += v * CX[q]; py += v * CY[q]; pz += v * CZ[q];
+        }
+    }
+    s[0][threadIdx.x] = m; s[1][threadIdx.x] = px; s[2][threadIdx.x] = py; s[3][threadIdx.x] = pz;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d)
+            for (int k = 0; k < 4; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+// Device address of `scratch` on each GPU, looked up once per device with
+// that device current (the array's name is only a host-side stand-in).
+static double* g_scratch_dev[64];
+static std::mutex g_scratch_mu;
+
+static hipError_t scratch_of_current_device(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = (double*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+long long noalloc_max_cells() { return NOALLOC_BLOCKS * NOALLOC_CELLS_PER_BLOCK; }
+
+hipError_t launch_field_stats_noalloc(const double* f, long long N, double* out, hipStream_t st) {
+    double* part = nullptr;
+    hipError_t e = scratch_of_current_device(&part);
+    if (e != hipSuccess) return e;
+    const int nblk = (int)((N + NOALLOC_CELLS_PER_BLOCK - 1) / NOALLOC_CELLS_PER_BLOCK);
+    if (nblk > NOALLOC_BLOCKS) return hipErrorInvalidValue;
+    if (nblk > 0) hipLaunchKernelGGL(k_field_stats_partial, dim3(nblk), dim3(256), 0, st, f, N, part);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, st, part, nblk, out);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

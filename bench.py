@@ -71,7 +71,8 @@ def measured_traffic(storage=0):
 
 
 def run_case(psm, torch, spec, storage, steps, warmup, autotune, launch=None, full_loop=True):
-    """Time `steps` coupled steps of one box. Returns a dict of results."""
+    """Time `steps` coupled steps of one box (a box without spheres when spec
+    has none). Returns a dict of results."""
     eng = psm.Engine([psm.desc_from_spec(spec)], storage=storage)
     N = spec.N
     with torch.cuda.stream(eng.stream):
@@ -247,11 +248,15 @@ def run_batched(psm, torch, inputs, steps=500, nbox=64):
 
 
 def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=False):
-    """Moving dense suspension: every step the forces are read back, the
-    spheres advance by explicit Euler on the host (density ratio 2.5), are
-    uploaded, re-binned and re-mapped. With device=True the same Euler update
-    and the re-binning run on the GPU (psm_integrate) with no per-step host
-    round trip; the forces are read once at the end."""
+    """Moving dense suspension advanced by explicit Euler (density ratio 2.5):
+    x_{n+1} = x_n + U_n, U_{n+1} = U_n + F_n/m, Omega_{n+1} = Omega_n + T_n/I.
+    Host form: every step the forces are read back and the spheres are
+    updated on the host; the new positions (which do not need the forces)
+    are computed and uploaded while the step runs (the upload and the device
+    re-binning are ordered after the step on its stream), the new velocities
+    once the forces are back. Device form (device=True): the same update and
+    the re-binning run on the GPU (psm_run) with no per-step host round trip;
+    the forces are read once at the end."""
     import numpy as np
 
     spec = inputs.dense_moving(n=n, seed=4)
@@ -265,46 +270,52 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
     del u0
     x, U, Om = spec.x.copy(), spec.U.copy(), spec.Om.copy()
     mass = 2.5 * 4.0 / 3.0 * np.pi * spec.r ** 3
-    inertia = 0.4 * mass * spec.r ** 2
+    inv_m = (1.0 / mass)[:, None]
+    inv_I = (1.0 / (0.4 * mass * spec.r ** 2))[:, None]
     L = np.asarray(spec.dims, dtype=np.float64)
+    eng.set_particles(0, x, spec.r, U, Om)
 
-    # per-module record of the host-driven loop: host times around each call,
-    # and events on the engine's stream around the upload + re-binning and
-    # the step launches
-    rec = {"set_particles": 0.0, "step_call": 0.0, "get_forces": 0.0, "euler": 0.0}
+    # per-module record of the host loop: host times around each call, and
+    # events on the engine's stream around the step launches and the
+    # position upload + re-binning
+    rec = {"step_call": 0.0, "positions": 0.0, "set_positions": 0.0, "get_forces": 0.0, "velocities": 0.0,
+           "set_velocities": 0.0}
     evs = []
 
     def one(record=False):
         nonlocal x, U, Om
+        t0 = time.perf_counter()
         if record:
             e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
             e[0].record(eng.stream)
-        t0 = time.perf_counter()
-        eng.set_particles(0, x, spec.r, U, Om)
-        t1 = time.perf_counter()
-        if record:
-            e[1].record(eng.stream)
         eng.step(1)
         if record:
-            e[2].record(eng.stream)
+            e[1].record(eng.stream)
+        t1 = time.perf_counter()
+        xn = x + U                         # x_{n+1} = x_n + U_n, while the step runs
+        np.mod(xn, L, out=xn)
         t2 = time.perf_counter()
-        F, T = eng.get_forces(0)
+        eng.set_particle_positions(0, xn)
+        if record:
+            e[2].record(eng.stream)
         t3 = time.perf_counter()
-        x = np.mod(x + U, L)
-        U = U + F / mass[:, None]
-        Om = Om + T / inertia[:, None]
+        F, T = eng.get_forces(0)           # waits for the step
         t4 = time.perf_counter()
+        U += F * inv_m
+        Om += T * inv_I
+        t5 = time.perf_counter()
+        eng.set_particle_velocities(0, U, Om)
+        t6 = time.perf_counter()
+        x = xn
         if record:
             evs.append(e)
-            rec["set_particles"] += t1 - t0
-            rec["step_call"] += t2 - t1
-            rec["get_forces"] += t3 - t2
-            rec["euler"] += t4 - t3
+            for k, dt_ in (("step_call", t1 - t0), ("positions", t2 - t1), ("set_positions", t3 - t2),
+                           ("get_forces", t4 - t3), ("velocities", t5 - t4), ("set_velocities", t6 - t5)):
+                rec[k] += dt_
 
     if device:
         # kernel time from an eager timed pass, wall time from graph replays
         # of 10 (step + update) pairs with the host out of the loop
-        eng.set_particles(0, x, spec.r, U, Om)
         eng.set_dynamics(0, 2.5)
         eng.reset_timing()
         eng.set_timing(True)
@@ -327,11 +338,12 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
         t0 = time.perf_counter()
         for _ in range(steps):
             one(record=True)
+        eng.get_forces(0)
         dt = time.perf_counter() - t0
         nl, kms = eng.get_timing()
         eng.set_timing(False)
-        up = sum(a.elapsed_time(b) for a, b, _ in evs) / steps
-        launches = sum(b.elapsed_time(c) for _, b, c in evs) / steps
+        launches = sum(a.elapsed_time(b) for a, b, _ in evs) / steps
+        upbin = sum(b.elapsed_time(c) for _, b, c in evs) / steps
         # the read-back alone: D2H of the forces and the synchronisation on an idle stream
         eng.synchronize()
         t0r = time.perf_counter()
@@ -339,16 +351,21 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
             eng.get_forces(0)
         d2h = (time.perf_counter() - t0r) * 1e3 / 20
         kern_ms = kms / max(nl, 1)
+        per = {k: v * 1e3 / steps for k, v in rec.items()}
         breakdown = {
-            "host_set_particles_ms": rec["set_particles"] * 1e3 / steps,
-            "host_euler_ms": rec["euler"] * 1e3 / steps,
-            "gpu_upload_and_binning_ms": up,
             "gpu_step_kernel_ms": kern_ms,
             "gpu_force_reduction_and_gaps_ms": launches - kern_ms,
+            "gpu_position_upload_and_binning_ms": upbin,
             "readback_d2h_sync_ms": d2h,
+            "host_position_update_ms (overlaps the step)": per["positions"],
+            "host_set_positions_call_ms (overlaps the step)": per["set_positions"],
+            "host_velocity_update_ms": per["velocities"],
+            "host_set_velocities_call_ms": per["set_velocities"],
+            "host_step_call_ms": per["step_call"],
+            "host_wait_in_get_forces_ms": per["get_forces"],
             "wall_ms": dt * 1e3 / steps,
-            "note": "host times measured around each call (set_particles enqueues the upload and the device "
-                    "re-binning without waiting); GPU times from events on the engine stream",
+            "note": "host times around each call; GPU times from events on the engine stream (the position "
+                    "upload and re-binning are ordered after the step and its force reduction)",
         }
     _, _, ov = eng.get_stats(0)
     kern0 = kernel_ms_without_spheres(eng) if device else None
@@ -364,7 +381,8 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
             "coupling_overhead_frac": (step_ms - kern) / step_ms, "launch": list(shape),
             "slot_overflows_last_map": ov,
             "particle_update": "device explicit Euler (psm_run: graphs of 10 step + update pairs)" if device
-                               else "host explicit Euler, upload, read-back"}
+                               else "host explicit Euler; positions uploaded while the step runs, velocities "
+                                    "after the force read-back"}
 
 
 def run_fluidized_bed(psm, torch, inputs, case, steps=200, warmup=5):
@@ -509,6 +527,8 @@ def main():
     ap.add_argument("--retune", action="store_true",
                     help="autotune the main run even where a committed counter run fixes its launch")
     ap.add_argument("--kernel-only", action="store_true", help="time psm_step alone (no upload/readback)")
+    ap.add_argument("--no-spheres", action="store_true",
+                    help="the main run's box without its spheres (the same fluid workload)")
     ap.add_argument("--storage", choices=list(STORAGE_OF), default="f64",
                     help="storage form of the main run (another than f64 skips the precision-form runs)")
     ap.add_argument("--precision-steps", type=int, default=None, help="steps of the FP32/FP16 runs (default --steps)")
@@ -552,6 +572,9 @@ def main():
     log(f"workload: {args.size}^3, {len(spec.r)} spheres, tau {spec.tau}, g {spec.fext[0]}")
 
     main_st = STORAGE_OF[args.storage]
+    if args.no_spheres:
+        import numpy as np
+        spec.x, spec.r, spec.U, spec.Om = np.zeros((0, 3)), np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3))
     main_launch = launch or counter_launch(main_st)
     log(f"{args.storage} main run" + (f" at the counter run's launch {main_launch}" if main_launch and not launch else ""))
     main_res = run_case(psm, torch, spec, main_st, args.steps, args.warmup, not args.no_autotune, main_launch,

@@ -149,6 +149,20 @@ int psm_get_macroscopic(psm_ctx* ctx, int box, double* rho, double* u);
 int psm_set_particles(psm_ctx* ctx, int box, int n, const double* x, const double* r,
                       const double* U, const double* omega);
 
+/* Update only the positions (host (n,3)) of the spheres of box `box`, with n
+ * the count of the last psm_set_particles; radii, velocities and the velocity
+ * Verlet state are kept. Positions are wrapped and checked as there; the tile
+ * lists are rebuilt on the device. Asynchronous (a host that integrates the
+ * spheres can upload the next positions while the current step runs: the
+ * upload is ordered after the step on the stream). Overflows are reported as
+ * for psm_set_particles. */
+int psm_set_particle_positions(psm_ctx* ctx, int box, int n, const double* x);
+
+/* Update only the velocities U and omega (host (n,3); NULL omega = 0) of the
+ * spheres of box `box`, n as above; no re-binning. Velocity Verlet starts
+ * again from these velocities. Asynchronous. */
+int psm_set_particle_velocities(psm_ctx* ctx, int box, int n, const double* U, const double* omega);
+
 /* Advance every box by nsteps time steps: per step, fused mapping +
  * stream-collide + force/torque partial sums (one launch over the tiles of all
  * boxes) and the per-particle reduction. With graphs enabled, runs of 10 steps
@@ -256,8 +270,18 @@ int psm_get_launch(psm_ctx* ctx, int* tx, int* ty, int* tz, int* flags);
  * one with the smallest mean of those two and report it (host outputs, each
  * may be NULL). The trial steps advance and overwrite the PDF state: set the
  * state after tuning. Synchronises. best_ms: ms per step of the chosen launch
- * in the second round. */
+ * in the second round.
+ * The pick is cached for the process, keyed by the GPU architecture, the
+ * storage form, the mapping and, per box, its dimensions, walls and sphere
+ * volume fraction (a power-of-two class); a context of a cached class gets
+ * the cached launch and time without any trial (its state is then not
+ * advanced). If the environment variable PSM_TUNE_CACHE names a file, its
+ * entries are read at the first call and new picks are appended to it. */
 int psm_autotune(psm_ctx* ctx, int trial_steps, int* tx, int* ty, int* tz, int* flags, double* best_ms);
+
+/* Forget the autotune picks of this process (the file named by
+ * PSM_TUNE_CACHE is not read again). Host-only call. */
+int psm_clear_tune_cache(void);
 
 /* Enable (1) / disable (0) HIP-graph replay of 10-step sequences in psm_step. */
 int psm_set_graph(psm_ctx* ctx, int enable);

@@ -58,6 +58,8 @@ _SIGS = {
     "psm_get_pdfs_at": ([_P, ctypes.c_int, ctypes.c_int, _P, _P], ctypes.c_int),
     "psm_get_macroscopic": ([_P, ctypes.c_int, _P, _P], ctypes.c_int),
     "psm_set_particles": ([_P, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D], ctypes.c_int),
+    "psm_set_particle_positions": ([_P, ctypes.c_int, ctypes.c_int, _D], ctypes.c_int),
+    "psm_set_particle_velocities": ([_P, ctypes.c_int, ctypes.c_int, _D, _D], ctypes.c_int),
     "psm_step": ([_P, ctypes.c_int], ctypes.c_int),
     "psm_get_forces": ([_P, ctypes.c_int, _D, _D], ctypes.c_int),
     "psm_get_solid_fraction": ([_P, ctypes.c_int, _P, _P], ctypes.c_int),
@@ -69,6 +71,7 @@ _SIGS = {
                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "psm_autotune": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _D], ctypes.c_int),
+    "psm_clear_tune_cache": ([], ctypes.c_int),
     "psm_set_graph": ([_P, ctypes.c_int], ctypes.c_int),
     "psm_set_timing": ([_P, ctypes.c_int], ctypes.c_int),
     "psm_get_timing": ([_P, ctypes.POINTER(ctypes.c_longlong), _D], ctypes.c_int),
@@ -192,6 +195,17 @@ def psm_set_particles(ctx, box, x, r, U, omega=None):
     return _check(lib().psm_set_particles(ctx, box, len(r), _dptr(x), _dptr(r), _dptr(U), _dptr(om)))
 
 
+def psm_set_particle_positions(ctx, box, x):
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+    return _check(lib().psm_set_particle_positions(ctx, box, len(x), _dptr(x)))
+
+
+def psm_set_particle_velocities(ctx, box, U, omega=None):
+    U = np.ascontiguousarray(U, dtype=np.float64).reshape(-1, 3)
+    om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64).reshape(-1, 3)
+    return _check(lib().psm_set_particle_velocities(ctx, box, len(U), _dptr(U), _dptr(om)))
+
+
 def psm_step(ctx, nsteps):
     return _check(lib().psm_step(ctx, int(nsteps)))
 
@@ -258,6 +272,10 @@ def psm_autotune(ctx, trial_steps):
     _check(lib().psm_autotune(ctx, int(trial_steps), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                               ctypes.byref(d), ctypes.byref(ms)))
     return (a.value, b.value, c.value, d.value), ms.value
+
+
+def psm_clear_tune_cache():
+    return _check(lib().psm_clear_tune_cache())
 
 
 def psm_set_graph(ctx, enable):
@@ -385,6 +403,12 @@ class Engine:
     def set_particles(self, box, x, r, U, omega=None):
         psm_set_particles(self.ctx, box, x, r, U, omega)
         self.np[box] = int(len(np.atleast_1d(r)))
+
+    def set_particle_positions(self, box, x):
+        psm_set_particle_positions(self.ctx, box, x)
+
+    def set_particle_velocities(self, box, U, omega=None):
+        psm_set_particle_velocities(self.ctx, box, U, omega)
 
     def step(self, n=1):
         psm_step(self.ctx, n)

@@ -16,6 +16,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -474,6 +476,38 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
         bx.pw[0] = bx.pref * W0;
         bx.pw[1] = bx.pref * W1;
         bx.pw[2] = bx.pref * W2;
+        bx.omega_f = (float)bx.omega;
+        for (int a = 0; a < 3; ++a) bx.g_f[a] = (float)bx.g[a];
+        for (int k = 0; k < 9; ++k) {
+            bx.fa_f[k] = (float)bx.fa[k];
+            bx.fs_f[k] = (float)bx.fs[k];
+            bx.fa_scaled_f[k] = (float)bx.fa_scaled[k];
+        }
+        for (int k = 0; k < 3; ++k) bx.pw_f[k] = (float)bx.pw[k];
+        {
+            // the FP16 form works on scale * d: quadratic terms carry 1/scale
+            const double inv_s = storage == PSM_FP16DEV ? 1.0 / fp16_scale : 1.0;
+            const double Wc[3] = {W0, W1, W2};
+            bx.om1 = 1.0 - bx.omega;
+            bx.k15 = 1.5 * inv_s;
+            bx.k45 = 4.5 * inv_s;
+            for (int c = 0; c < 3; ++c) {
+                bx.wk[c] = Wc[c] * bx.k45;
+                bx.owk[c] = bx.omega * bx.wk[c];
+                bx.ow3[c] = 3.0 * bx.omega * Wc[c];
+            }
+            bx.om1_f = (float)bx.om1;
+            bx.k15_f = (float)bx.k15;
+            bx.k45_f = (float)bx.k45;
+            for (int c = 0; c < 3; ++c) {
+                bx.wk_f[c] = (float)bx.wk[c];
+                bx.owk_f[c] = (float)bx.owk[c];
+                bx.ow3_f[c] = (float)bx.ow3[c];
+            }
+        }
+        // the FP32 reach test works on centres within a tile extent (at most
+        // 256 cells) plus the radius of the tile: a few FP32 ulps of that
+        bx.margin32 = 1e-3 + 16.0 * std::ldexp(256.0 + (d.max_particles > 0 ? d.max_radius : 1.0) + 2.0, -24);
         pb += d.max_particles;
     }
     c->d_boxes = (BoxDev*)(c->ws + L.off_boxes);
@@ -704,6 +738,85 @@ extern "C" int psm_set_particles(psm_ctx* c, int box, int n, const double* x, co
     rc = rebuild_lists_async(c);
     if (rc != PSM_OK) xr.clear();
     return rc;
+}
+
+// Upload some columns of the sphere table of box `box` (n spheres, the
+// current count) through the pinned staging: cols[k] (host, row-major (n,3))
+// goes to the three device columns first_col[k] .. first_col[k] + 2. Wraps
+// positions (first column 0) into the box. Asynchronous.
+static int upload_columns(psm_ctx* c, int box, int n, const double* const* cols, const int* first_col, int ncols) {
+    const psm_box_desc& d = c->desc[box];
+    const int m = d.max_particles;
+    const int h = c->stage_next;
+    c->stage_next ^= 1;
+    HIP_TRY(hipEventSynchronize(c->stage_ev[h]));
+    double* st = c->h_stage + (size_t)h * c->h_half;
+    const double L[3] = {(double)d.nx, (double)d.ny, (double)d.nz};
+    const int pb = c->box[box].part_base;
+    const size_t P1 = (size_t)std::max(c->P_total, 1);
+    double* dev_cols[11] = {c->P.x, c->P.y, c->P.z, c->P.r, c->P.fr, c->P.ux, c->P.uy, c->P.uz, c->P.ox, c->P.oy, c->P.oz};
+    for (int k = 0; k < ncols; ++k) {
+        double* sk = st + (size_t)3 * k * m;
+        const double* v = cols[k];
+        if (first_col[k] == 0) {
+            for (int p = 0; p < n; ++p)
+                for (int a = 0; a < 3; ++a) sk[(size_t)a * m + p] = wrap_coord(v[3 * p + a], L[a]);
+        } else {
+            for (int p = 0; p < n; ++p)
+                for (int a = 0; a < 3; ++a) sk[(size_t)a * m + p] = v ? v[3 * p + a] : 0.0;
+        }
+        // the three device columns are P_total apart: one strided copy
+        if (n > 0)
+            HIP_TRY(hipMemcpy2DAsync(dev_cols[first_col[k]] + pb, sizeof(double) * P1, sk, sizeof(double) * m,
+                                     sizeof(double) * n, 3, hipMemcpyHostToDevice, c->stream));
+    }
+    HIP_TRY(hipEventRecord(c->stage_ev[h], c->stream));
+    return PSM_OK;
+}
+
+static int check_update_args(psm_ctx* c, int box, int n) {
+    int rc = check_box(c, box);
+    if (rc) return rc;
+    if (n != c->np[box])
+        return fail(PSM_EINVAL, "box %d holds %d spheres (psm_set_particles), got %d", box, c->np[box], n);
+    return PSM_OK;
+}
+
+extern "C" int psm_set_particle_positions(psm_ctx* c, int box, int n, const double* x) {
+    int rc = check_update_args(c, box, n);
+    if (rc) return rc;
+    if (n > 0 && !x) return fail(PSM_EINVAL, "x is NULL");
+    const psm_box_desc& d = c->desc[box];
+    const int walled[3] = {d.walls_x, d.walls_y, d.walls_z};
+    const int dims3[3] = {d.nx, d.ny, d.nz};
+    const std::vector<double>& r = c->last_r[box];
+    for (int p = 0; p < n; ++p)
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(x[3 * p + a])) return fail(PSM_EINVAL, "particle %d: non-finite position", p);
+            if (walled[a] && !(x[3 * p + a] >= r[p] + 1.0 && x[3 * p + a] <= dims3[a] - r[p] - 1.0))
+                return fail(PSM_EINVAL, "particle %d: centre closer than r + 1 to a wall", p);
+        }
+    const double* cols[1] = {x};
+    const int first[1] = {0};
+    if ((rc = upload_columns(c, box, n, cols, first, 1))) return rc;
+    c->last_xr[box].clear();   // positions changed outside psm_set_particles
+    return rebuild_lists_async(c);
+}
+
+extern "C" int psm_set_particle_velocities(psm_ctx* c, int box, int n, const double* U, const double* omega) {
+    int rc = check_update_args(c, box, n);
+    if (rc) return rc;
+    if (n > 0 && !U) return fail(PSM_EINVAL, "U is NULL");
+    for (int p = 0; p < n; ++p)
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(U[3 * p + a]) || (omega && !std::isfinite(omega[3 * p + a])))
+                return fail(PSM_EINVAL, "particle %d: non-finite velocity", p);
+    const double* cols[2] = {U, omega};
+    const int first[2] = {5, 8};
+    if ((rc = upload_columns(c, box, n, cols, first, 2))) return rc;
+    // new velocities: velocity Verlet starts again from this state
+    HIP_TRY(launch_fill_int(c->P.prev_ok + c->box[box].part_base, c->desc[box].max_particles, 0, c->stream));
+    return PSM_OK;
 }
 
 static int step_params(psm_ctx* c, int parity, StepParams& kp) {
@@ -1089,10 +1202,117 @@ extern "C" int psm_reset_timing(psm_ctx* c) {
     return PSM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotune cache: the launch picked for a class of contexts, kept for the
+// process and, if PSM_TUNE_CACHE names a file, across processes (one line per
+// entry: key, tx, ty, tz, flags, ms per step).
+
+struct TuneEntry {
+    TileShape ts;
+    double ms;
+};
+static std::mutex g_tune_mu;
+static std::map<std::string, TuneEntry> g_tune;
+static bool g_tune_loaded = false;
+
+// The class of a context: GPU architecture, storage form, mapping, and per
+// box its dimensions, walls and sphere volume fraction (rounded to a power
+// of two in hundredths): the quantities the best launch depends on.
+static std::string tune_key(psm_ctx* c) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string arch = "?";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s|s%d|m%d|n%d", arch.c_str(), c->storage, c->map_mode, c->nbox);
+    std::string k = buf;
+    for (int b = 0; b < c->nbox; ++b) {
+        const psm_box_desc& d = c->desc[b];
+        double vol = 0.0;
+        for (double r : c->last_r[b]) vol += 4.18879020478639098 * r * r * r;
+        const double frac = vol / ((double)d.nx * d.ny * d.nz);
+        const int cls = frac <= 0.0 ? -1 : (int)std::lround(std::log2(std::max(frac * 100.0, 1e-3)));
+        std::snprintf(buf, sizeof buf, "|%dx%dx%d:%d%d%d:%d", d.nx, d.ny, d.nz, d.walls_x, d.walls_y, d.walls_z, cls);
+        k += buf;
+    }
+    return k;
+}
+
+static void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("PSM_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char key[4096];
+    TuneEntry e{};
+    while (std::fscanf(f, "%4095s %d %d %d %d %d %lf", key, &e.ts.tx, &e.ts.ty, &e.ts.tz, &e.ts.persistent,
+                       &e.ts.filter, &e.ms) == 7)
+        if (shape_allowed(e.ts.tx, e.ts.ty, e.ts.tz)) g_tune[key] = e;
+    std::fclose(f);
+}
+
+static void tune_store_locked(const std::string& key, const TuneEntry& e) {
+    g_tune[key] = e;
+    const char* path = std::getenv("PSM_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d %d %d %.6f\n", key.c_str(), e.ts.tx, e.ts.ty, e.ts.tz, e.ts.persistent, e.ts.filter,
+                 e.ms);
+    std::fclose(f);
+}
+
+extern "C" int psm_clear_tune_cache(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
+    g_tune_loaded = true;   // entries of the file are not read again in this process
+    return PSM_OK;
+}
+
+static int autotune_timed(psm_ctx* c, int trial_steps, TileShape& best, double& best_t);
+
 extern "C" int psm_autotune(psm_ctx* c, int trial_steps, int* tx, int* ty, int* tz, int* flags,
                             double* best_ms) {
     if (!c) return fail(PSM_EINVAL, "ctx is NULL");
     if (trial_steps < 1) return fail(PSM_EINVAL, "trial_steps must be >= 1");
+    const std::string key = tune_key(c);
+    TuneEntry hit{};
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            hit = it->second;
+            cached = true;
+        }
+    }
+    TileShape best;
+    double best_t = 0.0;
+    int rc;
+    if (cached) {
+        best = hit.ts;
+        best_t = hit.ms;
+        rc = psm_set_launch(c, best.tx, best.ty, best.tz, launch_flags(best));
+        if (rc) return rc;
+    } else {
+        rc = autotune_timed(c, trial_steps, best, best_t);
+        if (rc) return rc;
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        tune_store_locked(key, TuneEntry{best, best_t});
+    }
+    if (tx) *tx = best.tx;
+    if (ty) *ty = best.ty;
+    if (tz) *tz = best.tz;
+    if (flags) *flags = launch_flags(best);
+    if (best_ms) *best_ms = best_t;
+    return PSM_OK;
+}
+
+// Time every allowed launch on the context and keep the fastest (see psm.h).
+static int autotune_timed(psm_ctx* c, int trial_steps, TileShape& best_out, double& best_ms_out) {
     bool was_timing = c->timing, was_graph = c->use_graph;
     c->timing = false;
     c->use_graph = false;
@@ -1168,11 +1388,8 @@ extern "C" int psm_autotune(psm_ctx* c, int trial_steps, int* tx, int* ty, int* 
     if (cands.empty()) return fail(PSM_EINVAL, "no launch shape is allowed for these boxes");
     rc = psm_set_launch(c, best.tx, best.ty, best.tz, launch_flags(best));
     if (rc) return rc;
-    if (tx) *tx = best.tx;
-    if (ty) *ty = best.ty;
-    if (tz) *tz = best.tz;
-    if (flags) *flags = launch_flags(best);
-    if (best_ms) *best_ms = best_t;
+    best_out = best;
+    best_ms_out = best_t;
     return PSM_OK;
 }
 

@@ -13,7 +13,10 @@ constexpr int NWAVE = WG / 64;   // 64-wide wavefronts per workgroup
 constexpr int MAXC = 64;         // sphere candidates per tile staged in LDS
 constexpr int TZ_MAX = 32;   // largest cells per thread along z of a tile
 constexpr int NXCD = 8;          // MI355X: 8 accelerator complex dies, 32 CUs each
-constexpr int BLK = 64;          // cells per PDF storage block (one wavefront)
+#ifndef PSM_BLK
+#define PSM_BLK 64
+#endif
+constexpr int BLK = PSM_BLK;     // cells per PDF storage block (one wavefront)
 
 // D3Q19 velocity set in the canonical order of the ABI (psm.h). Directions
 // come in inverse pairs (2k-1, 2k) for k = 1..9.
@@ -44,6 +47,15 @@ struct BoxDev {
     double fa[9], fs[9];            // 3 pref w (c.g), 9 pref w (c.g)
     double fa_scaled[9];            // fa times the FP16 storage scale
     double pw[3];                   // pref w for the rest, axis and diagonal weights
+    // Collision constants per weight class c (rest, axis, diagonal) with the
+    // FP16 storage scale s folded in (s = 1 otherwise):
+    //   k15 = 1.5/s, k45 = 4.5/s, wk[c] = W_c k45, owk[c] = omega W_c k45, ow3[c] = 3 omega W_c
+    double om1, k15, k45, wk[3], owk[3], ow3[3];
+    // FP32 copies of the collision constants for the deviation forms
+    float omega_f, g_f[3], fa_f[9], fs_f[9], fa_scaled_f[9], pw_f[3];
+    float om1_f, k15_f, k45_f, wk_f[3], owk_f[3], ow3_f[3];
+    // rounding margin (cells) of the step kernel's FP32 reach test
+    double margin32;
     // Geometry constants for the minimum image and the sub-sample test.
     double L[3], halfL[3];          // box lengths and their halves
     double sub_off[16];             // (k + 1/2)/nsub - 1/2, k < nsub

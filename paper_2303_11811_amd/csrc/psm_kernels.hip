@@ -20,31 +20,45 @@
 
 namespace psm {
 
-#define GLOBAL __attribute__((address_space(1)))
-typedef const GLOBAL char GCHAR;
+// ---------------------------------------------------------------------------
+// PDF access of the step kernel through buffer resources. A resource covers
+// one z-plane of a grid (raw bytes, fewer than 2^31); every load or store
+// takes the cell's byte offset inside the plane per lane and the run of its
+// direction (q * 64 values) as a scalar offset, so that no per-access 64-bit
+// address arithmetic runs on the vector ALU.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
+constexpr int RSRC_WORD3 = 0x00020000;   // raw 32-bit data format, no swizzle
 
 // Cache policy of the PDF streams (compile-time switches, measured by the
-// autotuning sweeps): nontemporal stores / loads bypass cache retention.
+// tuning sweeps): nontemporal stores / loads bypass cache retention.
 #ifndef PSM_NT_STORE
 #define PSM_NT_STORE 1
 #endif
 #ifndef PSM_NT_LOAD
 #define PSM_NT_LOAD 0
 #endif
-template <class T> __device__ __forceinline__ T ld_pdf(const GLOBAL T* p) {
-#if PSM_NT_LOAD
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
+constexpr int LD_AUX = PSM_NT_LOAD ? 2 : 0;
+constexpr int ST_AUX = PSM_NT_STORE ? 2 : 0;
+
+#ifndef PSM_BUFFER_IO
+#define PSM_BUFFER_IO 1
 #endif
+#if PSM_BUFFER_IO
+__device__ __forceinline__ Rsrc plane_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, RSRC_WORD3);
 }
-template <class T> __device__ __forceinline__ void st_pdf(GLOBAL T* p, T v) {
-#if PSM_NT_STORE
-    __builtin_nontemporal_store(v, p);
+#define PSM_LD(B, T, r, vo, so) __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_##B(r, vo, so, LD_AUX))
+#define PSM_ST(B, U, v, r, vo, so) __builtin_amdgcn_raw_buffer_store_##B(__builtin_bit_cast(U, v), r, vo, so, ST_AUX)
 #else
-    *p = v;
+// plain global accesses from the plane's base address (compile-time alternative)
+typedef const char* RsrcPtr;
+#define Rsrc RsrcPtr
+__device__ __forceinline__ Rsrc plane_rsrc(const void* base, unsigned) { return (const char*)base; }
+#define GLB __attribute__((address_space(1)))
+#define PSM_LD(B, T, r, vo, so) (*(const GLB T*)((r) + (so) + (vo)))
+#define PSM_ST(B, U, v, r, vo, so) __builtin_nontemporal_store(v, (GLB decltype(v)*)((r) + (so) + (vo)))
 #endif
-}
 
 // ---------------------------------------------------------------------------
 // Storage traits: FP64 stores f; the deviation forms store d = f - w_q
@@ -54,8 +68,8 @@ struct St64 {
     using R = double;
     static constexpr bool DEV = false;
     static constexpr bool SCALED = false;
-    __device__ static R loadb(const GCHAR* b, unsigned off, float) { return ld_pdf((const GLOBAL T*)(b + off)); }
-    __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float) { st_pdf((GLOBAL T*)(b + off), v); }
+    __device__ static R ld(Rsrc r, unsigned vo, int so) { return PSM_LD(b64, double, r, vo, so); }
+    __device__ static void st(Rsrc r, unsigned vo, int so, R v) { PSM_ST(b64, u32x2, v, r, vo, so); }
     __device__ static double to_f64(T v, float) { return v; }
     __device__ static T from_f64(double v, float) { return v; }
 };
@@ -64,8 +78,8 @@ struct St32 {
     using R = float;
     static constexpr bool DEV = true;
     static constexpr bool SCALED = false;
-    __device__ static R loadb(const GCHAR* b, unsigned off, float) { return ld_pdf((const GLOBAL T*)(b + off)); }
-    __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float) { st_pdf((GLOBAL T*)(b + off), v); }
+    __device__ static R ld(Rsrc r, unsigned vo, int so) { return PSM_LD(b32, float, r, vo, so); }
+    __device__ static void st(Rsrc r, unsigned vo, int so, R v) { PSM_ST(b32, unsigned int, v, r, vo, so); }
     __device__ static double to_f64(T v, float) { return (double)v; }
     __device__ static T from_f64(double v, float) { return (float)v; }
 };
@@ -77,12 +91,24 @@ struct St16 {
     // scale s is folded into the collision constants), so its loads and
     // stores are bare conversions. State I/O converts with the scale.
     static constexpr bool SCALED = true;
-    __device__ static R loadb(const GCHAR* b, unsigned off, float) { return (float)ld_pdf((const GLOBAL T*)(b + off)); }
-    __device__ static void storeb(GLOBAL char* b, unsigned off, R v, float) { st_pdf((GLOBAL T*)(b + off), (_Float16)v); }
+    __device__ static R ld(Rsrc r, unsigned vo, int so) { return (float)PSM_LD(b16, _Float16, r, vo, so); }
+    __device__ static void st(Rsrc r, unsigned vo, int so, R v) {
+        const _Float16 h = (_Float16)v;
+        PSM_ST(b16, unsigned short, h, r, vo, so);
+    }
     // scale is a power of two: multiplication by it and by 1/scale is exact
     __device__ static double to_f64(T v, float inv) { return (double)((float)v * inv); }
     __device__ static T from_f64(double v, float scale) { return (_Float16)(float)(v * (double)scale); }
 };
+
+// The box constant of the collision's precision R: the FP64 value or its
+// FP32 copy (both set by the host).
+template <class R> __device__ __forceinline__ R pick(double d, float f);
+template <> __device__ __forceinline__ double pick<double>(double d, float) { return d; }
+template <> __device__ __forceinline__ float pick<float>(double, float f) { return f; }
+
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 __device__ inline int find_box(const int* tile_base, int nbox, int t) {
     int lo = 0, hi = nbox - 1;
@@ -99,11 +125,18 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// Cross-lane moves of a double. DPP forms stay inside a row of 16 lanes and
-// run on the vector ALU: quad permutations, the mirror inside each half row
-// (lane i <-> 7 - i of its group of 8) and the rotation of a row by 8 (lane
-// i <-> i ^ 8). Lane i ^ 16 comes from a swizzle inside 32 lanes, lane i ^ 32
-// from a permute.
+// ---------------------------------------------------------------------------
+// Cross-lane moves on the vector ALU. DPP forms stay inside a row of 16
+// lanes: quad permutations, the mirror inside each half row (lane i <-> 7 - i
+// of its group of 8) and the rotation of a row by 8 (lane i <-> i ^ 8).
+// Across rows, the gfx950 swaps exchange odd with even rows (lanes i and
+// i ^ 16) and the two halves of the wave (lanes i and i ^ 32): with both
+// operands the same value v, the two results are v at the lower partner and
+// v at the upper partner, so their sum is the pair sum, taken in the same
+// order on both lanes.
+template <int CTRL> __device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
 template <int CTRL> __device__ __forceinline__ double dpp_f64(double v) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
@@ -114,43 +147,61 @@ constexpr int DPP_QUAD_XOR1 = 0xB1;         // quad_perm [1, 0, 3, 2]
 constexpr int DPP_QUAD_XOR2 = 0x4E;         // quad_perm [2, 3, 0, 1]
 constexpr int DPP_ROW_HALF_MIRROR = 0x141;
 constexpr int DPP_ROW_ROR8 = 0x128;
-__device__ __forceinline__ double swizzle_xor16(double v) {
-    // bit mode: and mask 0x1f, or mask 0, xor mask 0x10
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_ds_swizzle((int)b, 0x401F);
-    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
 
-// Wave sums of six values at once. Inside each group of 8 lanes a butterfly
-// splits the values (padded to 8) between exchanging lanes: the mirror pair
-// by bit 2 of the lane, then quad partners by bits 1 and 0 (7 exchanges),
-// after which lane l holds the group's sum of value l & 7; three exchanges
-// across groups finish the sums. All within-group moves are DPP. Every lane
-// returns the total of value `comp` = l & 7 (values 6 and 7 are padding).
-// The order of the additions is fixed, so the result is reproducible bit for
-// bit, and partners add the same two numbers, so all lanes of one value agree.
-__device__ inline double wave_sum6(const double v[6], int lane, int& comp) {
+__device__ __forceinline__ float pair_sum16(float v) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float pair_sum32(float v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double join(unsigned lo, unsigned hi) {
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double pair_sum16(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const auto l = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    return join(l[0], h[0]) + join(l[1], h[1]);
+}
+__device__ __forceinline__ double pair_sum32(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const auto l = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    return join(l[0], h[0]) + join(l[1], h[1]);
+}
+template <int CTRL> __device__ __forceinline__ float dppv(float v) { return dpp_f32<CTRL>(v); }
+template <int CTRL> __device__ __forceinline__ double dppv(double v) { return dpp_f64<CTRL>(v); }
+
+// Wave sums of six values at once (V = float or double). Inside each group
+// of 8 lanes a butterfly splits the values (padded to 8) between exchanging
+// lanes: the mirror pair by bit 2 of the lane, then quad partners by bits 1
+// and 0 (7 exchanges), after which lane l holds the group's sum of value
+// l & 7; three exchanges across groups (row rotation by 8, the row swap, the
+// half swap) finish the sums. Lane l returns the total of value l & 7
+// (values 6 and 7 are padding). The order of the additions is fixed, so the
+// result is reproducible bit for bit.
+template <class V>
+__device__ inline V wave_sum6(const V v[6], int lane) {
     const bool b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
-    double a[4], b[2];
+    V a[4], b[2];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const double lo = v[i], hi = i + 4 < 6 ? v[i + 4] : 0.0;
-        const double keep = b2 ? hi : lo, send = b2 ? lo : hi;
-        a[i] = keep + dpp_f64<DPP_ROW_HALF_MIRROR>(send);
+        const V lo = v[i], hi = i + 4 < 6 ? v[i + 4] : (V)0;
+        const V keep = b2 ? hi : lo, send = b2 ? lo : hi;
+        a[i] = keep + dppv<DPP_ROW_HALF_MIRROR>(send);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        const double keep = b1 ? a[i + 2] : a[i], send = b1 ? a[i] : a[i + 2];
-        b[i] = keep + dpp_f64<DPP_QUAD_XOR2>(send);
+        const V keep = b1 ? a[i + 2] : a[i], send = b1 ? a[i] : a[i + 2];
+        b[i] = keep + dppv<DPP_QUAD_XOR2>(send);
     }
-    const double keep = b0 ? b[1] : b[0], send = b0 ? b[0] : b[1];
-    double d = keep + dpp_f64<DPP_QUAD_XOR1>(send);
-    d += dpp_f64<DPP_ROW_ROR8>(d);
-    d += swizzle_xor16(d);
-    d += __shfl_xor(d, 32, 64);
-    comp = lane & 7;
-    return d;
+    const V keep = b0 ? b[1] : b[0], send = b0 ? b[0] : b[1];
+    V d = keep + dppv<DPP_QUAD_XOR1>(send);
+    d += dppv<DPP_ROW_ROR8>(d);
+    d = pair_sum16(d);
+    return pair_sum32(d);
 }
 
 // Uniform (wave-invariant) data is read through the constant address space so
@@ -160,114 +211,162 @@ template <class T> __device__ __forceinline__ const PSM_CONST T* cptr(const T* p
     return (const PSM_CONST T*)p;
 }
 
-// One inverse pair (q, q+1) of the plain SRT update with forcing:
-//   E_q(U) = w (rho + 3 c.U + 4.5 (c.U)^2 - 1.5 U.U) = s + a, E_qbar(U) = s - a  (eq. 5)
-//   t_q = (E_q(U) - f_q)/tau + F_q      (eq. 3; eq. 8 with the Guo prefactor)
-//   f~_q = f_q + t_q
-// rho is the density deviation for the deviation storage forms.
+// ---------------------------------------------------------------------------
+// Lattice products of direction Q with only its nonzero terms (D3Q19
+// components are 0 or +-1; at most two are nonzero), in x, y, z order.
+template <int C, class R> __device__ __forceinline__ R cterm(R v) { return C > 0 ? v : -v; }
+template <class R, int Q> __device__ __forceinline__ R cdot(R x, R y, R z) {
+    constexpr int a = CX[Q], b = CY[Q], c = CZ[Q];
+    if constexpr (a != 0 && b != 0) return cterm<a>(x) + cterm<b>(y);
+    else if constexpr (a != 0 && c != 0) return cterm<a>(x) + cterm<c>(z);
+    else if constexpr (b != 0 && c != 0) return cterm<b>(y) + cterm<c>(z);
+    else if constexpr (a != 0) return cterm<a>(x);
+    else if constexpr (b != 0) return cterm<b>(y);
+    else if constexpr (c != 0) return cterm<c>(z);
+    else return (R)0;
+}
+// c.M.c for a symmetric M given as the diagonal (Mxx, Myy, Mzz) and the
+// doubled off-diagonal terms (2 Mxy, 2 Mxz, 2 Myz).
 template <class R, int Q>
-__device__ __forceinline__ void pair_fluid(R& fq, R& fb, R base, R Ux, R Uy, R Uz, R fa, R fs, R pwUg3,
-                                           R omega, R k45) {
-    constexpr R w = (R)wq(Q);
-    constexpr R cx = (R)CX[Q], cy = (R)CY[Q], cz = (R)CZ[Q];
-    R cu = cx * Ux + cy * Uy + cz * Uz;
-    R sU = w * base + (k45 * w) * (cu * cu);
-    R aU = ((R)3.0 * w) * cu;
-    R Fs = fs * cu - pwUg3;
-    fq = fq + (omega * (sU + aU - fq) + (Fs + fa));
-    fb = fb + (omega * (sU - aU - fb) + (Fs - fa));
+__device__ __forceinline__ R cmc(R Mxx, R Myy, R Mzz, R Mxy2, R Mxz2, R Myz2) {
+    constexpr int a = CX[Q], b = CY[Q], c = CZ[Q];
+    if constexpr (a != 0 && b != 0) return (a * b > 0) ? (Mxx + Myy) + Mxy2 : (Mxx + Myy) - Mxy2;
+    else if constexpr (a != 0 && c != 0) return (a * c > 0) ? (Mxx + Mzz) + Mxz2 : (Mxx + Mzz) - Mxz2;
+    else if constexpr (b != 0 && c != 0) return (b * c > 0) ? (Myy + Mzz) + Myz2 : (Myy + Mzz) - Myz2;
+    else if constexpr (a != 0) return Mxx;
+    else if constexpr (b != 0) return Myy;
+    else return Mzz;
+}
+
+// Per weight class W (axis or diagonal) of a cell: the terms of the SRT
+// update with forcing (eqs. 3, 5, 8) that do not depend on the direction.
+//   E_q(U) = W (base + k45 (c.U)^2) + 3 W (c.U) = s + a,  E_qbar(U) = s - a,
+//   F_q = fa + fs (c.U) - pu,  F_qbar = -fa + fs (c.U) - pu,  base = rho - k15 U.U
+template <class R>
+struct WClass {
+    R Wb;      // W base (per cell)
+    R owb_pu;  // omega W base - pu (per cell)
+    R Wk;      // W k45 (box constant)
+    R W3;      // 3 W
+    R owk;     // omega W k45 (box constant)
+    R ow3;     // 3 omega W (box constant)
+};
+
+// One inverse pair (q, q+1) of the plain update f~ = f + omega (E - f) + F:
+//   f~_q = (1 - omega) f_q + P + A,  f~_qbar = (1 - omega) f_qbar + P - A,
+//   P = omega s + fs (c.U) - pu,  A = omega a + fa.
+template <class R, int Q>
+__device__ __forceinline__ void pair_fluid(R& fq, R& fb, R cu, const WClass<R>& w, R fa, R fs, R om1) {
+    const R P = fmar(fs, cu, fmar(w.owk, cu * cu, w.owb_pu));
+    const R A = fmar(w.ow3, cu, fa);
+    fq = fmar(om1, fq, P + A);
+    fb = fmar(om1, fb, P - A);
 }
 
 // The same pair under PSM (eqs. 17-19):
-//   f~_q = f_q + (1-B) t_q + B (f_qbar - E_qbar(U) - f_q) + sum_s B_s E_q(U_p,s)
+//   f~_q = f_q + (1-B) t_q + B (f_qbar - E_qbar(U) - f_q) + sum_s B_s E_q(V_s),
+//   t_q = omega (E_q(U) - f_q) + F_q = P + A - omega f_q,
 // with the slot sum folded into ten cell scalars:
-//   sum_s B_s E_q(V_s) = w (A0 + 4.5 c.M.c) + 3 w c.P,
-//   A0 = sum_s B_s (rho - 1.5 V_s.V_s), M = sum_s B_s V_s V_s^T, P = sum_s B_s V_s.
+//   sum_s B_s E_q(V_s) = W (A0 + k45 c.M.c) + 3 W c.P = sV + aV,
+//   A0 = sum_s B_s (rho - k15 V_s.V_s), M = sum_s B_s V_s V_s^T, P = sum_s B_s V_s.
 template <class R, int Q>
-__device__ __forceinline__ void pair_psm(R& fq, R& fb, R base, R Ux, R Uy, R Uz, R fa, R fs, R pwUg3, R omega,
-                                         R k45, R Bt, R omB, R A0, R Mxx, R Myy, R Mzz, R Mxy, R Mxz, R Myz,
-                                         R Px, R Py, R Pz) {
-    constexpr R w = (R)wq(Q);
-    constexpr int ix = CX[Q], iy = CY[Q], iz = CZ[Q];
-    constexpr R cx = (R)ix, cy = (R)iy, cz = (R)iz;
-    R cu = cx * Ux + cy * Uy + cz * Uz;
-    R sU = w * base + (k45 * w) * (cu * cu);
-    R aU = ((R)3.0 * w) * cu;
-    R Fs = fs * cu - pwUg3;
-    R tq = omega * (sU + aU - fq) + (Fs + fa);
-    R tb = omega * (sU - aU - fb) + (Fs - fa);
-    R cMc = (R)(ix * ix) * Mxx + (R)(iy * iy) * Myy + (R)(iz * iz) * Mzz +
-            (R)(2 * ix * iy) * Mxy + (R)(2 * ix * iz) * Mxz + (R)(2 * iy * iz) * Myz;
-    R cP = cx * Px + cy * Py + cz * Pz;
-    R sV = w * A0 + (k45 * w) * cMc;
-    R aV = ((R)3.0 * w) * cP;
-    R Sq = Bt * (fb - (sU - aU) - fq) + (sV + aV);
-    R Sb = Bt * (fq - (sU + aU) - fb) + (sV - aV);
-    R nq = (fq + omB * tq) + Sq;
-    R nb = (fb + omB * tb) + Sb;
+__device__ __forceinline__ void pair_psm(R& fq, R& fb, R cu, const WClass<R>& w, R fa, R fs, R omega, R Bt, R omB,
+                                         R WA0, R cM, R cP) {
+    const R cu2 = cu * cu;
+    const R s = fmar(w.Wk, cu2, w.Wb);
+    const R a = w.W3 * cu;
+    const R P = fmar(fs, cu, fmar(w.owk, cu2, w.owb_pu));
+    const R A = fmar(w.ow3, cu, fa);
+    const R sV = fmar(w.Wk, cM, WA0);
+    const R aV = w.W3 * cP;
+    const R D = fb - fq;
+    const R tq = fmar(-omega, fq, P + A);
+    const R tb = fmar(-omega, fb, P - A);
+    const R nq = fmar(omB, tq, fq) + fmar(Bt, (D - s) + a, sV + aV);
+    const R nb = fmar(omB, tb, fb) + fmar(Bt, (-D - s) - a, sV - aV);
     fq = nq;
     fb = nb;
 }
 
 // Lever arm d = x - x_p (minimum image, taken in FP64) and particle velocity
-// at the cell centre (eq. 20) times the storage scale sc, in the collision's
-// precision R: FP64 for FP64 storage, FP32 for the deviation forms.
-template <class R>
-__device__ __forceinline__ void slot_geometry(int c, double cxc, double cyc, double czc, double Lx, double hLx,
-                                              double Ly, double hLy, double Lz, double hLz, const double* px,
-                                              const double* py, const double* pz, const double* ux,
-                                              const double* uy, const double* uz, const double* ox,
-                                              const double* oy, const double* oz, R sc, R& dx, R& dy, R& dz,
-                                              R& Vx, R& Vy, R& Vz) {
-    dx = (R)min_image(cxc - px[c], Lx, hLx);
-    dy = (R)min_image(cyc - py[c], Ly, hLy);
-    dz = (R)min_image(czc - pz[c], Lz, hLz);
-    Vx = sc * ((R)ux[c] + ((R)oy[c] * dz - (R)oz[c] * dy));
-    Vy = sc * ((R)uy[c] + ((R)oz[c] * dx - (R)ox[c] * dz));
-    Vz = sc * ((R)uz[c] + ((R)ox[c] * dy - (R)oy[c] * dx));
+// at the cell centre (eq. 20) in FP64 (FP64 storage).
+__device__ __forceinline__ void slot_geometry64(int c, double cxc, double cyc, double czc, double Lx, double hLx,
+                                                double Ly, double hLy, double Lz, double hLz, const double* px,
+                                                const double* py, const double* pz, const double* ux,
+                                                const double* uy, const double* uz, const double* ox,
+                                                const double* oy, const double* oz, double& dx, double& dy,
+                                                double& dz, double& Vx, double& Vy, double& Vz) {
+    dx = min_image(cxc - px[c], Lx, hLx);
+    dy = min_image(cyc - py[c], Ly, hLy);
+    dz = min_image(czc - pz[c], Lz, hLz);
+    Vx = ux[c] + (oy[c] * dz - oz[c] * dy);
+    Vy = uy[c] + (oz[c] * dx - ox[c] * dz);
+    Vz = uz[c] + (ox[c] * dy - oy[c] * dx);
 }
 
+// Minimum image in FP32 of a displacement that is within a few box lengths.
+__device__ __forceinline__ float wrap32(float t, float L, float invL) { return fmar(-L, __builtin_rintf(t * invL), t); }
+
 // Waves per SIMD the register budget of the step kernel is cut for: 3 for
-// FP64 and FP16 storage (168 VGPRs), 4 for FP32 storage (128 VGPRs). Under
-// the 128-register cap the FP16 form serialises its 19 loads.
+// FP64 storage (168 VGPRs), 4 for the deviation forms (128 VGPRs).
 #ifndef PSM_WAVES_PER_EU
 #define PSM_WAVES_PER_EU 3
 #endif
-#ifndef PSM_WAVES_PER_EU_F32
-#define PSM_WAVES_PER_EU_F32 4
+#ifndef PSM_WAVES_PER_EU_DEV
+#define PSM_WAVES_PER_EU_DEV 4
+#endif
+// Pull order of the step kernel (measured per storage form): the FP32 form
+// pulls the next cell's values while it works on the current one; FP64 and
+// FP16 pull each cell's values after its mapping (pulling earlier, or ahead,
+// cost FP64 registers spilled to scratch and did not speed up FP16).
+#ifndef PSM_PREFETCH_F32
+#define PSM_PREFETCH_F32 1
+#endif
+#ifndef PSM_PREFETCH_F16
+#define PSM_PREFETCH_F16 0
+#endif
+#ifndef PSM_EARLY_PULLS
+#define PSM_EARLY_PULLS 0
 #endif
 
-// pull of the 19 values of one cell: planes z (bz), z-1 (bm), z+1 (bp)
-#define PSM_LOAD19(F, bz, bm, bp)                      \
-    do {                                               \
-        F[0] = S::loadb(bz + 0 * QB, o00, kp.h_inv);   \
-        F[1] = S::loadb(bz + 1 * QB, om0, kp.h_inv);   \
-        F[2] = S::loadb(bz + 2 * QB, op0, kp.h_inv);   \
-        F[3] = S::loadb(bz + 3 * QB, o0m, kp.h_inv);   \
-        F[4] = S::loadb(bz + 4 * QB, o0p, kp.h_inv);   \
-        F[5] = S::loadb(bm + 5 * QB, o00, kp.h_inv);   \
-        F[6] = S::loadb(bp + 6 * QB, o00, kp.h_inv);   \
-        F[7] = S::loadb(bz + 7 * QB, omm, kp.h_inv);   \
-        F[8] = S::loadb(bz + 8 * QB, opp, kp.h_inv);   \
-        F[9] = S::loadb(bz + 9 * QB, omp, kp.h_inv);   \
-        F[10] = S::loadb(bz + 10 * QB, opm, kp.h_inv); \
-        F[11] = S::loadb(bm + 11 * QB, om0, kp.h_inv); \
-        F[12] = S::loadb(bp + 12 * QB, op0, kp.h_inv); \
-        F[13] = S::loadb(bp + 13 * QB, om0, kp.h_inv); \
-        F[14] = S::loadb(bm + 14 * QB, op0, kp.h_inv); \
-        F[15] = S::loadb(bm + 15 * QB, o0m, kp.h_inv); \
-        F[16] = S::loadb(bp + 16 * QB, o0p, kp.h_inv); \
-        F[17] = S::loadb(bp + 17 * QB, o0m, kp.h_inv); \
-        F[18] = S::loadb(bm + 18 * QB, o0p, kp.h_inv); \
+// pull of the 19 values of one cell from the source planes z (rz), z-1 (rm)
+// and z+1 (rp); direction q lies q * QB bytes into a block
+#define PSM_LOAD19(F, rz, rm, rp)            \
+    do {                                     \
+        F[0] = S::ld(rz, o00, 0 * QB);       \
+        F[1] = S::ld(rz, om0, 1 * QB);       \
+        F[2] = S::ld(rz, op0, 2 * QB);       \
+        F[3] = S::ld(rz, o0m, 3 * QB);       \
+        F[4] = S::ld(rz, o0p, 4 * QB);       \
+        F[5] = S::ld(rm, o00, 5 * QB);       \
+        F[6] = S::ld(rp, o00, 6 * QB);       \
+        F[7] = S::ld(rz, omm, 7 * QB);       \
+        F[8] = S::ld(rz, opp, 8 * QB);       \
+        F[9] = S::ld(rz, omp, 9 * QB);       \
+        F[10] = S::ld(rz, opm, 10 * QB);     \
+        F[11] = S::ld(rm, om0, 11 * QB);     \
+        F[12] = S::ld(rp, op0, 12 * QB);     \
+        F[13] = S::ld(rp, om0, 13 * QB);     \
+        F[14] = S::ld(rm, op0, 14 * QB);     \
+        F[15] = S::ld(rm, o0m, 15 * QB);     \
+        F[16] = S::ld(rp, o0p, 16 * QB);     \
+        F[17] = S::ld(rp, o0m, 17 * QB);     \
+        F[18] = S::ld(rm, o0p, 18 * QB);     \
     } while (0)
+
 template <class S, int MAP, bool FILT>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typename S::T) == 4 ? PSM_WAVES_PER_EU_F32 : PSM_WAVES_PER_EU, 8))) void k_psm_step(
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S::DEV ? PSM_WAVES_PER_EU_DEV : PSM_WAVES_PER_EU, 8))) void k_psm_step(
     StepParams kp) {
     using R = typename S::R;
     using T = typename S::T;
 
     __shared__ double s_px[MAXC], s_py[MAXC], s_pz[MAXC], s_pr[MAXC], s_pfr[MAXC];
     __shared__ double s_ux[MAXC], s_uy[MAXC], s_uz[MAXC], s_ox[MAXC], s_oy[MAXC], s_oz[MAXC];
+    // FP32 copies: centre relative to the tile centre (minimum image), the
+    // squared reach of the overlap test with a rounding margin, and (for the
+    // deviation forms) the velocities
+    __shared__ float s_qx[MAXC], s_qy[MAXC], s_qz[MAXC], s_lim2[MAXC];
+    __shared__ float s_uf[6][MAXC];
     __shared__ int s_pid[MAXC];
     __shared__ double s_acc[NWAVE][6][MAXC];
     __shared__ unsigned long long s_cmask[NWAVE][TZ_MAX];
@@ -314,15 +413,28 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
         const int tcz = lt / (ntx * nty);
         const int e0 = tile_off[t];
         const int nc = tile_off[t + 1] - e0;   // at most MAXC: the scan caps every list
+        const double Lx = bx.L[0], Ly = bx.L[1], Lz = bx.L[2];
+        const double hLx = bx.halfL[0], hLy = bx.halfL[1], hLz = bx.halfL[2];
+        // tile centre in cell coordinates
+        const double tmx = tcx * TX + 0.5 * TX, tmy = tcy * TY + 0.5 * TY, tmz = tcz * TZ + 0.5 * TZ;
 
         if (nc > 0) {
             for (int c = tid; c < nc; c += WG) {
                 int p = kp.tile_pid[e0 + c];
                 s_pid[c] = p;
-                s_px[c] = kp.P.x[p]; s_py[c] = kp.P.y[p]; s_pz[c] = kp.P.z[p];
-                s_pr[c] = kp.P.r[p]; s_pfr[c] = kp.P.fr[p];
-                s_ux[c] = kp.P.ux[p]; s_uy[c] = kp.P.uy[p]; s_uz[c] = kp.P.uz[p];
-                s_ox[c] = kp.P.ox[p]; s_oy[c] = kp.P.oy[p]; s_oz[c] = kp.P.oz[p];
+                const double px = kp.P.x[p], py = kp.P.y[p], pz = kp.P.z[p], pr = kp.P.r[p], pfr = kp.P.fr[p];
+                s_px[c] = px; s_py[c] = py; s_pz[c] = pz;
+                s_pr[c] = pr; s_pfr[c] = pfr;
+                s_qx[c] = (float)min_image(px - tmx, Lx, hLx);
+                s_qy[c] = (float)min_image(py - tmy, Ly, hLy);
+                s_qz[c] = (float)min_image(pz - tmz, Lz, hLz);
+                const double lim = pr + (lin_map ? pfr : bx.reach) + bx.margin32;
+                s_lim2[c] = (float)(lim * lim);
+                const double u[6] = {kp.P.ux[p], kp.P.uy[p], kp.P.uz[p], kp.P.ox[p], kp.P.oy[p], kp.P.oz[p]};
+                s_ux[c] = u[0]; s_uy[c] = u[1]; s_uz[c] = u[2];
+                s_ox[c] = u[3]; s_oy[c] = u[4]; s_oz[c] = u[5];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) s_uf[k][c] = (float)u[k];
             }
             for (int i = tid; i < NWAVE * 6 * MAXC; i += WG) (&s_acc[0][0][0])[i] = 0.0;
         }
@@ -335,7 +447,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
         const int xm = xs == 0 ? nx - 1 : xs - 1, xp = xs == nx - 1 ? 0 : xs + 1;
         const int ym = ys == 0 ? ny - 1 : ys - 1, yp = ys == ny - 1 ? 0 : ys + 1;
         // byte offsets inside a z-plane of the nine (x, y) source columns;
-        // they do not depend on z
+        // they do not depend on z (a plane holds fewer than 2^31 bytes)
         const int pitch = bx.pitch;
         auto inplane = [pitch](int xx, int yy) -> unsigned {
             int c = xx + pitch * yy;
@@ -350,18 +462,22 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
         const unsigned o0m = inplane(xs, ym), o0p = inplane(xs, yp);
         const unsigned omm = inplane(xm, ym), opp = inplane(xp, yp), omp = inplane(xm, yp), opm = inplane(xp, ym);
         const long long pbytes = bx.plane_elems * (long long)sizeof(T);
-        const T* __restrict__ src = (const T*)bx.grid[kp.parity];
-        T* __restrict__ dst = (T*)bx.grid[kp.parity ^ 1];
-        const R omega = (R)bx.omega;
-        const R gx = (R)bx.g[0], gy = (R)bx.g[1], gz = (R)bx.g[2];
+        const unsigned pb32 = (unsigned)pbytes;
+        const char* src = (const char*)bx.grid[kp.parity];
+        const char* dst = (const char*)bx.grid[kp.parity ^ 1];
+        const R omega = pick<R>(bx.omega, bx.omega_f);
+        const R om1 = pick<R>(bx.om1, bx.om1_f);
+        const R gx = pick<R>(bx.g[0], bx.g_f[0]), gy = pick<R>(bx.g[1], bx.g_f[1]), gz = pick<R>(bx.g[2], bx.g_f[2]);
         // scaled storage (FP16): the kernel works on s d; the quadratic terms
         // carry 1/s and every particle velocity is multiplied by s
         const R sc = S::SCALED ? (R)kp.h_scale : (R)1;
-        const R k15 = S::SCALED ? (R)1.5 * (R)kp.h_inv : (R)1.5;
-        const R k45 = S::SCALED ? (R)4.5 * (R)kp.h_inv : (R)4.5;
-        const double Lx = bx.L[0], Ly = bx.L[1], Lz = bx.L[2];
-        const double hLx = bx.halfL[0], hLy = bx.halfL[1], hLz = bx.halfL[2];
+        const R k15 = pick<R>(bx.k15, bx.k15_f);
+        const R k45 = pick<R>(bx.k45, bx.k45_f);
         const double cxc = xs + 0.5, cyc = ys + 0.5;
+        // this cell's centre relative to the tile centre (FP32, exact)
+        const float rx = (float)(lx + 0.5 - 0.5 * TX), ry = (float)(ly + 0.5 - 0.5 * TY);
+        const float Lxf = (float)Lx, Lyf = (float)Ly, Lzf = (float)Lz;
+        const float iLx = 1.0f / Lxf, iLy = 1.0f / Lyf, iLz = 1.0f / Lzf;
         // Candidate filter: bit c of s_cmask[wave][k] is set if candidate c
         // can reach a cell of this wave at the tile's k-th z: the distance from
         // the sphere centre to the rectangle of the wave's cell centres (lanes
@@ -393,31 +509,75 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
 
         constexpr int QB = BLK * (int)sizeof(T);
 
+        // Latency hiding: PREF pulls the next cell's 19 values (one cell up in
+        // z) while the current one is mapped and collided; EARLY issues the
+        // current cell's pulls before its mapping.
+        constexpr bool PREF = S::DEV && (S::SCALED ? PSM_PREFETCH_F16 : PSM_PREFETCH_F32);
+        constexpr bool EARLY = !PREF && PSM_EARLY_PULLS;
+        R fn[NQ];
+        if constexpr (PREF) {
+            const int z0 = tcz * TZ;
+            if (lane_ok && z0 < nz) {
+                const int zm0 = z0 == 0 ? nz - 1 : z0 - 1, zp0 = z0 == nz - 1 ? 0 : z0 + 1;
+                const Rsrc a = plane_rsrc(src + z0 * pbytes, pb32), am = plane_rsrc(src + zm0 * pbytes, pb32),
+                           ap = plane_rsrc(src + zp0 * pbytes, pb32);
+                PSM_LOAD19(fn, a, am, ap);
+            }
+        }
+
         for (int k = 0; k < TZ; ++k) {
             const int z = tcz * TZ + k;
             if (z >= nz) break;
             const double czc = z + 0.5;
+            const float rz = (float)(k + 0.5 - 0.5 * TZ);
             const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-            // scalar plane bases of the source planes z-1, z, z+1 and the
-            // destination plane z; directions are 64 values apart in a block
-            const GCHAR* sbz = (const GCHAR*)src + z * pbytes;
-            const GCHAR* sbm = (const GCHAR*)src + zm * pbytes;
-            const GCHAR* sbp = (const GCHAR*)src + zp * pbytes;
-            GLOBAL char* dbz = (GLOBAL char*)dst + z * pbytes;
+            // buffer resources of the source planes z, z-1, z+1 and the
+            // destination plane z
+            const Rsrc sz = plane_rsrc(src + z * pbytes, pb32);
+            const Rsrc sm = plane_rsrc(src + zm * pbytes, pb32);
+            const Rsrc sp = plane_rsrc(src + zp * pbytes, pb32);
+            const Rsrc dz_ = plane_rsrc(dst + z * pbytes, pb32);
+
+            // 2a. pull: f_q(x) = grid[q][x - c_q] (eq. 2 read backwards)
+            R f[NQ];
+            if constexpr (PREF) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) f[q] = fn[q];
+                const int z1 = z + 1;
+                if (lane_ok && k + 1 < TZ && z1 < nz) {
+                    // planes z + 1 (own), z (below) and z + 2 (above, periodic)
+                    const Rsrc a2 = plane_rsrc(src + (z1 == nz - 1 ? 0 : z1 + 1) * pbytes, pb32);
+                    PSM_LOAD19(fn, sp, sz, a2);
+                }
+            } else if constexpr (EARLY) {
+                if (lane_ok) PSM_LOAD19(f, sz, sm, sp);
+            }
 
             // 1. solid fractions of this cell from the staged candidates (Sec. 2.3.2);
-            // with the filter, only the candidates that can reach this wave at this z
+            // with the filter, only the candidates that can reach this wave at this z.
+            // In the deviation forms an FP32 test with a margin first rejects the
+            // candidates out of reach. The fraction itself is FP64, bit for bit that
+            // of the read-out path.
             int c0 = -1, c1 = -1;
             double B0 = 0.0, B1 = 0.0;
             int dropped = 0;   // overlaps beyond the two slots at this cell
 #define PSM_MAP_ONE(c)                                                                                       \
     do {                                                                                                    \
-        double dx = min_image(cxc - s_px[c], Lx, hLx);                                                      \
-        double dy = min_image(cyc - s_py[c], Ly, hLy);                                                      \
-        double dz = min_image(czc - s_pz[c], Lz, hLz);                                                      \
-        double B = lin_map ? overlap_linear(dx, dy, dz, s_pr[c], s_pfr[c])                                  \
-                            : overlap_subsample(dx, dy, dz, s_pr[c], bx.nsub, bx.sub_off, bx.reach);         \
-        if (B > 0.0) slots_insert(sl, c, s_pid[c], B);                                                      \
+        bool near_ = true;                                                                                  \
+        if constexpr (S::DEV) {                                                                             \
+            const float tx_ = wrap32(rx - s_qx[c], Lxf, iLx);                                               \
+            const float ty_ = wrap32(ry - s_qy[c], Lyf, iLy);                                               \
+            const float tz_ = wrap32(rz - s_qz[c], Lzf, iLz);                                               \
+            near_ = fmar(tz_, tz_, fmar(ty_, ty_, tx_ * tx_)) <= s_lim2[c];                                 \
+        }                                                                                                   \
+        if (near_) {                                                                                        \
+            double dx = min_image(cxc - s_px[c], Lx, hLx);                                                  \
+            double dy = min_image(cyc - s_py[c], Ly, hLy);                                                  \
+            double dz = min_image(czc - s_pz[c], Lz, hLz);                                                  \
+            double B = lin_map ? overlap_linear(dx, dy, dz, s_pr[c], s_pfr[c])                              \
+                               : overlap_subsample(dx, dy, dz, s_pr[c], bx.nsub, bx.sub_off, bx.reach);     \
+            if (B > 0.0) slots_insert(sl, c, s_pid[c], B);                                                  \
+        }                                                                                                   \
     } while (0)
             if constexpr (FILT) {
                 unsigned long long cm = nc > 0 ? s_cmask[wave][k] : 0ull;
@@ -449,7 +609,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
             // once per wave; the host reports it in strict-slot mode
             if (psm_wave && __ballot(dropped != 0) != 0ull && lane == 0) atomicOr(kp.flags, FLAG_SLOT_OVERFLOW);
 
-            // 2. pull: f_q(x) = grid[q][x - c_q]
+            // 2b. boundaries of the pulled values
             R hx = 0, hy = 0, hz = 0;   // 2 j - U, for the force of eq. (21)
             if (lane_ok) {
                 // through a face (first and last z plane of a box with walls):
@@ -467,7 +627,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
 #pragma unroll
                         for (int i = 0; i < 5; ++i) {
                             const int q = w == 0 ? in0[i] : in1[i];
-                            fb[i] = S::loadb(sbz + inv_dir(q) * QB, o00, kp.h_inv) + ws * (R)bx.bw[w][q];
+                            fb[i] = S::ld(sz, o00, inv_dir(q) * QB) + ws * (R)bx.bw[w][q];
                         }
                     } else {
                         // anti-bounce-back with the cell's post-collision velocity
@@ -475,7 +635,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
                         R ux = 0, uy = 0, uz = 0;
 #pragma unroll
                         for (int q = 1; q < NQ; ++q) {
-                            const R v = S::loadb(sbz + q * QB, o00, kp.h_inv);
+                            const R v = S::ld(sz, o00, q * QB);
                             ux += (R)CX[q] * v; uy += (R)CY[q] * v; uz += (R)CZ[q] * v;
                         }
                         const R rw = S::DEV ? (R)(bx.face_rho[w] - 1.0) * sc : (R)bx.face_rho[w];
@@ -484,13 +644,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
                         for (int i = 0; i < 5; ++i) {
                             const int q = w == 0 ? in0[i] : in1[i];
                             const R cu = (R)CX[q] * ux + (R)CY[q] * uy + (R)CZ[q] * uz;
-                            fb[i] = (R)(2.0 * wq(q)) * (rw + k45 * (cu * cu) - uu) -
-                                    S::loadb(sbz + inv_dir(q) * QB, o00, kp.h_inv);
+                            fb[i] = (R)(2.0 * wq(q)) * (rw + k45 * (cu * cu) - uu) - S::ld(sz, o00, inv_dir(q) * QB);
                         }
                     }
                 }
-                R f[NQ];
-                PSM_LOAD19(f, sbz, sbm, sbp);
+                if constexpr (!PREF && !EARLY) PSM_LOAD19(f, sz, sm, sp);
                 if (face_plane) {
                     if (z == 0) {
                         f[5] = fb[0]; f[11] = fb[1]; f[14] = fb[2]; f[15] = fb[3]; f[18] = fb[4];
@@ -506,88 +664,125 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
                     for (int q = 1; q < NQ; ++q) {
                         const bool hit = (CX[q] == 1 && (edge & 1)) || (CX[q] == -1 && (edge & 2)) ||
                                          (CY[q] == 1 && (edge & 4)) || (CY[q] == -1 && (edge & 8));
-                        if (hit) f[q] = S::loadb(sbz + inv_dir(q) * QB, o00, kp.h_inv);
+                        if (hit) f[q] = S::ld(sz, o00, inv_dir(q) * QB);
                     }
                 }
 
-                // 3. moments, eqs. (6)-(7); U carries the f/2 shift
-                R rho = ((((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) +
-                         (((f[8] + f[9]) + (f[10] + f[11])) + ((f[12] + f[13]) + (f[14] + f[15])))) +
-                        ((f[16] + f[17]) + f[18]);
-                R jx = ((f[1] - f[2]) + (f[7] - f[8])) + ((f[9] - f[10]) + (f[11] - f[12])) + (f[13] - f[14]);
-                R jy = ((f[3] - f[4]) + (f[7] - f[8])) + ((f[10] - f[9]) + (f[15] - f[16])) + (f[17] - f[18]);
-                R jz = ((f[5] - f[6]) + (f[11] - f[12])) + ((f[14] - f[13]) + (f[15] - f[16])) + (f[18] - f[17]);
+                // 3. moments, eqs. (6)-(7), accumulated from the sum and the
+                // difference of each inverse pair (q, q+1), q = 2k-1 with c_q =
+                // +x, +y, +z, (1,1,0), (1,-1,0), (1,0,1), (1,0,-1), (0,1,1),
+                // (0,1,-1) for k = 1..9; U carries the f/2 shift
+                R rho = f[0], jx, jy, jz;
+                {
+                    R d;
+                    rho += f[1] + f[2]; jx = f[1] - f[2];
+                    rho += f[3] + f[4]; jy = f[3] - f[4];
+                    rho += f[5] + f[6]; jz = f[5] - f[6];
+                    rho += f[7] + f[8]; d = f[7] - f[8]; jx += d; jy += d;
+                    rho += f[9] + f[10]; d = f[9] - f[10]; jx += d; jy -= d;
+                    rho += f[11] + f[12]; d = f[11] - f[12]; jx += d; jz += d;
+                    rho += f[13] + f[14]; d = f[13] - f[14]; jx += d; jz -= d;
+                    rho += f[15] + f[16]; d = f[15] - f[16]; jy += d; jz += d;
+                    rho += f[17] + f[18]; d = f[17] - f[18]; jy += d; jz -= d;
+                }
                 const R half = (R)0.5;
-                R Ux = jx + half * (sc * gx), Uy = jy + half * (sc * gy), Uz = jz + half * (sc * gz);
-                R uu = Ux * Ux + Uy * Uy + Uz * Uz;
-                R base = rho - k15 * uu;
-                R Ug3 = (R)3.0 * (Ux * gx + Uy * gy + Uz * gz);
-                const R pu0 = (R)bx.pw[0] * Ug3, pu1 = (R)bx.pw[1] * Ug3, pu2 = (R)bx.pw[2] * Ug3;
+                const R Ux = fmar(half, sc * gx, jx), Uy = fmar(half, sc * gy, jy), Uz = fmar(half, sc * gz, jz);
+                const R uu = fmar(Uz, Uz, fmar(Uy, Uy, Ux * Ux));
+                const R base = fmar(-k15, uu, rho);
+                const R Ug3 = (R)3.0 * fmar(Uz, gz, fmar(Uy, gy, Ux * gx));
+                const R pu0 = pick<R>(bx.pw[0], bx.pw_f[0]) * Ug3;
+                WClass<R> w1, w2;
+                {
+                    constexpr R W1r = (R)W1, W2r = (R)W2;
+                    w1.Wb = W1r * base; w2.Wb = W2r * base;
+                    w1.W3 = (R)3 * W1r; w2.W3 = (R)3 * W2r;
+                    w1.Wk = pick<R>(bx.wk[1], bx.wk_f[1]); w2.Wk = pick<R>(bx.wk[2], bx.wk_f[2]);
+                    w1.owk = pick<R>(bx.owk[1], bx.owk_f[1]); w2.owk = pick<R>(bx.owk[2], bx.owk_f[2]);
+                    w1.ow3 = pick<R>(bx.ow3[1], bx.ow3_f[1]); w2.ow3 = pick<R>(bx.ow3[2], bx.ow3_f[2]);
+                    w1.owb_pu = fmar(omega, w1.Wb, -pick<R>(bx.pw[1], bx.pw_f[1]) * Ug3);
+                    w2.owb_pu = fmar(omega, w2.Wb, -pick<R>(bx.pw[2], bx.pw_f[2]) * Ug3);
+                }
+#define PSM_FA(Q) pick<R>(S::SCALED ? bx.fa_scaled[Q / 2] : bx.fa[Q / 2], S::SCALED ? bx.fa_scaled_f[Q / 2] : bx.fa_f[Q / 2])
+#define PSM_FS(Q) pick<R>(bx.fs[Q / 2], bx.fs_f[Q / 2])
+#define PSM_STORE(Q) S::st(dz_, o00, (Q) * QB, f[Q])
 
                 // 4. collision; each pair is stored as soon as it is final
-#define PSM_STORE(Q) S::storeb(dbz + (Q) * QB, o00, f[Q], kp.h_scale)
                 if (!psm_wave) {
-                    f[0] = f[0] + (omega * ((R)W0 * base - f[0]) - pu0);
+                    f[0] = fmar(om1, f[0], fmar(omega * (R)W0, base, -pu0));
                     PSM_STORE(0);
-#define PSM_PAIR(Q)                                                                                           \
-    pair_fluid<R, Q>(f[Q], f[Q + 1], base, Ux, Uy, Uz, (R)(S::SCALED ? bx.fa_scaled[Q / 2] : bx.fa[Q / 2]),  \
-                     (R)bx.fs[Q / 2], Q < 7 ? pu1 : pu2, omega, k45);                                         \
-    PSM_STORE(Q);                                                                                             \
+#define PSM_PAIR(Q)                                                                                 \
+    pair_fluid<R, Q>(f[Q], f[Q + 1], cdot<R, Q>(Ux, Uy, Uz), Q < 7 ? w1 : w2, PSM_FA(Q), PSM_FS(Q), om1); \
+    PSM_STORE(Q);                                                                                   \
     PSM_STORE(Q + 1)
                     PSM_PAIR(1); PSM_PAIR(3); PSM_PAIR(5); PSM_PAIR(7); PSM_PAIR(9);
                     PSM_PAIR(11); PSM_PAIR(13); PSM_PAIR(15); PSM_PAIR(17);
 #undef PSM_PAIR
                 } else {
                     hx = (R)2 * jx - Ux; hy = (R)2 * jy - Uy; hz = (R)2 * jz - Uz;
-                    // slot terms with U_p(x) of eq. (20)
+                    // slot terms with U_p(x) of eq. (20) (times the storage scale)
+                    // (a wave with a slot somewhere: lanes without one add nothing)
                     R Bt = 0, A0 = 0, Mxx = 0, Myy = 0, Mzz = 0, Mxy = 0, Mxz = 0, Myz = 0, Px = 0, Py = 0, Pz = 0;
-                    if (c0 >= 0) {
-                        R dx, dy, dz, Vx, Vy, Vz;
-                        slot_geometry<R>(c0, cxc, cyc, czc, Lx, hLx, Ly, hLy, Lz, hLz, s_px, s_py, s_pz, s_ux, s_uy,
-                                         s_uz, s_ox, s_oy, s_oz, sc, dx, dy, dz, Vx, Vy, Vz);
-                        const R Bs = (R)B0;
-                        Bt = Bs;
-                        A0 = Bs * (rho - k15 * (Vx * Vx + Vy * Vy + Vz * Vz));
-                        Px = Bs * Vx; Py = Bs * Vy; Pz = Bs * Vz;
-                        Mxx = Px * Vx; Myy = Py * Vy; Mzz = Pz * Vz;
-                        Mxy = Px * Vy; Mxz = Px * Vz; Myz = Py * Vz;
-                    }
-                    if (c1 >= 0) {
-                        R dx, dy, dz, Vx, Vy, Vz;
-                        slot_geometry<R>(c1, cxc, cyc, czc, Lx, hLx, Ly, hLy, Lz, hLz, s_px, s_py, s_pz, s_ux, s_uy,
-                                         s_uz, s_ox, s_oy, s_oz, sc, dx, dy, dz, Vx, Vy, Vz);
-                        const R Bs = (R)B1;
-                        Bt = Bt + Bs;
-                        A0 = A0 + Bs * (rho - k15 * (Vx * Vx + Vy * Vy + Vz * Vz));
-                        R qx = Bs * Vx, qy = Bs * Vy, qz = Bs * Vz;
-                        Px = Px + qx; Py = Py + qy; Pz = Pz + qz;
-                        Mxx = Mxx + qx * Vx; Myy = Myy + qy * Vy; Mzz = Mzz + qz * Vz;
-                        Mxy = Mxy + qx * Vy; Mxz = Mxz + qx * Vz; Myz = Myz + qy * Vz;
+#pragma unroll
+                    for (int sl = 0; sl < 2; ++sl) {
+                        const int c = sl == 0 ? c0 : c1;
+                        if (c < 0) continue;   // slot 1 is only filled after slot 0
+                        R Vx, Vy, Vz;
+                        if constexpr (S::DEV) {
+                            // lever arm from the FP32 tile-relative centre
+                            const float dx = wrap32(rx - s_qx[c], Lxf, iLx);
+                            const float dy = wrap32(ry - s_qy[c], Lyf, iLy);
+                            const float dz = wrap32(rz - s_qz[c], Lzf, iLz);
+                            Vx = sc * (s_uf[0][c] + (s_uf[4][c] * dz - s_uf[5][c] * dy));
+                            Vy = sc * (s_uf[1][c] + (s_uf[5][c] * dx - s_uf[3][c] * dz));
+                            Vz = sc * (s_uf[2][c] + (s_uf[3][c] * dy - s_uf[4][c] * dx));
+                        } else {
+                            double dx, dy, dz;
+                            slot_geometry64(c, cxc, cyc, czc, Lx, hLx, Ly, hLy, Lz, hLz, s_px, s_py, s_pz, s_ux,
+                                            s_uy, s_uz, s_ox, s_oy, s_oz, dx, dy, dz, Vx, Vy, Vz);
+                        }
+                        const R Bs = (R)(sl == 0 ? B0 : B1);
+                        const R qx = Bs * Vx, qy = Bs * Vy, qz = Bs * Vz;
+                        const R a0 = Bs * fmar(-k15, fmar(Vz, Vz, fmar(Vy, Vy, Vx * Vx)), rho);
+                        if (sl == 0) {
+                            Bt = Bs; A0 = a0; Px = qx; Py = qy; Pz = qz;
+                            Mxx = qx * Vx; Myy = qy * Vy; Mzz = qz * Vz;
+                            Mxy = qx * Vy; Mxz = qx * Vz; Myz = qy * Vz;
+                        } else {
+                            Bt = Bt + Bs; A0 = A0 + a0;
+                            Px = Px + qx; Py = Py + qy; Pz = Pz + qz;
+                            Mxx = fmar(qx, Vx, Mxx); Myy = fmar(qy, Vy, Myy); Mzz = fmar(qz, Vz, Mzz);
+                            Mxy = fmar(qx, Vy, Mxy); Mxz = fmar(qx, Vz, Mxz); Myz = fmar(qy, Vz, Myz);
+                        }
                     }
                     const R omB = (R)1 - Bt;
+                    const R Mxy2 = Mxy + Mxy, Mxz2 = Mxz + Mxz, Myz2 = Myz + Myz;
+                    const R WA01 = (R)W1 * A0, WA02 = (R)W2 * A0;
                     {
                         constexpr R w = (R)W0;
-                        R s0 = w * base;
-                        R t0 = omega * (s0 - f[0]) - pu0;
-                        f[0] = (f[0] + omB * t0) + (w * A0 - Bt * s0);
+                        const R s0 = w * base;
+                        const R t0 = fmar(omega, s0 - f[0], -pu0);
+                        f[0] = fmar(omB, t0, f[0]) + fmar(-Bt, s0, w * A0);
                         PSM_STORE(0);
                     }
-#define PSM_PAIR(Q)                                                                                       \
-    pair_psm<R, Q>(f[Q], f[Q + 1], base, Ux, Uy, Uz, (R)(S::SCALED ? bx.fa_scaled[Q / 2] : bx.fa[Q / 2]),     \
-                   (R)bx.fs[Q / 2], Q < 7 ? pu1 : pu2, omega, k45, Bt, omB, A0, Mxx, Myy, Mzz, Mxy, Mxz, Myz, Px, \
-                   Py, Pz);                                                                                      \
-    PSM_STORE(Q);                                                                                                \
+#define PSM_PAIR(Q)                                                                                           \
+    pair_psm<R, Q>(f[Q], f[Q + 1], cdot<R, Q>(Ux, Uy, Uz), Q < 7 ? w1 : w2, PSM_FA(Q), PSM_FS(Q), omega, Bt, omB, \
+                   Q < 7 ? WA01 : WA02, cmc<R, Q>(Mxx, Myy, Mzz, Mxy2, Mxz2, Myz2), cdot<R, Q>(Px, Py, Pz));        \
+    PSM_STORE(Q);                                                                                             \
     PSM_STORE(Q + 1)
                     PSM_PAIR(1); PSM_PAIR(3); PSM_PAIR(5); PSM_PAIR(7); PSM_PAIR(9);
                     PSM_PAIR(11); PSM_PAIR(13); PSM_PAIR(15); PSM_PAIR(17);
 #undef PSM_PAIR
                 }
 #undef PSM_STORE
+#undef PSM_FA
+#undef PSM_FS
             }
 
             // 5. force and torque of eqs. (21)-(22): sum_q C^solid_{q,s} c_qbar
             // = 2 j - U - U_p(x) per slot (first moment of eq. 19); per-sphere
-            // wave sums accumulated per wave in LDS in a fixed order.
+            // wave sums accumulated per wave in LDS in FP64 in a fixed order.
+            // The deviation forms compute each cell's share and the wave sum in
+            // FP32 (the collision's precision); FP64 storage does both in FP64.
             if (psm_wave) {
                 int pend0 = lane_ok ? c0 : -1, pend1 = lane_ok ? c1 : -1;
                 while (true) {
@@ -600,25 +795,31 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(sizeof(typen
                     double Bs = 0.0;
                     if (pend0 == c) { Bs = B0; pend0 = -1; }
                     else if (pend1 == c) { Bs = B1; pend1 = -1; }
-                    double v[6] = {0, 0, 0, 0, 0, 0};
+                    R v[6] = {0, 0, 0, 0, 0, 0};
                     if (Bs != 0.0) {
-                        // this cell's share in the collision's precision; the
-                        // sums over cells and tiles are FP64
                         R dx, dy, dz, Vx, Vy, Vz;
-                        slot_geometry<R>(c, cxc, cyc, czc, Lx, hLx, Ly, hLy, Lz, hLz, s_px, s_py, s_pz, s_ux, s_uy,
-                                         s_uz, s_ox, s_oy, s_oz, sc, dx, dy, dz, Vx, Vy, Vz);
+                        if constexpr (S::DEV) {
+                            dx = wrap32(rx - s_qx[c], Lxf, iLx);
+                            dy = wrap32(ry - s_qy[c], Lyf, iLy);
+                            dz = wrap32(rz - s_qz[c], Lzf, iLz);
+                            Vx = sc * (s_uf[0][c] + (s_uf[4][c] * dz - s_uf[5][c] * dy));
+                            Vy = sc * (s_uf[1][c] + (s_uf[5][c] * dx - s_uf[3][c] * dz));
+                            Vz = sc * (s_uf[2][c] + (s_uf[3][c] * dy - s_uf[4][c] * dx));
+                        } else {
+                            slot_geometry64(c, cxc, cyc, czc, Lx, hLx, Ly, hLy, Lz, hLz, s_px, s_py, s_pz, s_ux,
+                                            s_uy, s_uz, s_ox, s_oy, s_oz, dx, dy, dz, Vx, Vy, Vz);
+                        }
                         const R Bh = (R)(S::SCALED ? Bs * (double)kp.h_inv : Bs);
                         const R fx = Bh * (hx - Vx), fy = Bh * (hy - Vy), fz = Bh * (hz - Vz);
-                        v[0] = (double)fx;
-                        v[1] = (double)fy;
-                        v[2] = (double)fz;
-                        v[3] = (double)(dy * fz - dz * fy);
-                        v[4] = (double)(dz * fx - dx * fz);
-                        v[5] = (double)(dx * fy - dy * fx);
+                        v[0] = fx;
+                        v[1] = fy;
+                        v[2] = fz;
+                        v[3] = dy * fz - dz * fy;
+                        v[4] = dz * fx - dx * fz;
+                        v[5] = dx * fy - dy * fx;
                     }
-                    int comp;
-                    const double sum = wave_sum6(v, lane, comp);
-                    if (lane < 6) s_acc[wave][comp][c] += sum;
+                    const R sum = wave_sum6<R>(v, lane);
+                    if (lane < 6) s_acc[wave][lane][c] += (double)sum;
                 }
             }
         }

@@ -167,3 +167,56 @@ def test_run_replays_graphs_bitwise():
             assert np.array_equal(u, v), (n, dt)
     for eng in engines:
         eng.close()
+
+
+def test_host_coupling_with_split_updates_matches_oracle():
+    """The host-driven explicit Euler loop of the moving suspension with the
+    split updates: the next positions are uploaded right after the step is
+    enqueued (ordered after it on the stream, so the step and its force
+    reduction see the old ones), the new velocities after the force
+    read-back. Matches the oracle's step + integrator sequence, and the same
+    loop with one full psm_set_particles per step bit for bit."""
+    spec = inputs.random_small((44, 36, 30), 5, (2.5, 4.0), seed=23, tau=0.65, fext=(1e-5, 0.0, -4e-6),
+                               vamp=0.1, omamp=0.004)
+    steps = 8
+    box = oracle_box(spec)
+    f = initial_f(spec)
+    dyn = oracle.Dynamics(spec.x, spec.r, spec.U, spec.Om)
+    for _ in range(steps):
+        ref = oracle.run(box, f, 1, dyn.x, dyn.r, dyn.U, dyn.Om)
+        f = ref.f
+        oracle.integrate(box, dyn, ref.F, ref.T, dt=1.0, scheme=oracle.EULER, rho_p=1.0)
+    m = 4.0 / 3.0 * np.pi * spec.r ** 3
+    inv_m, inv_I = (1.0 / m)[:, None], (1.0 / (0.4 * m * spec.r ** 2))[:, None]
+    L = np.asarray(spec.dims, dtype=np.float64)
+    results = []
+    for split in (True, False):
+        eng = make_engine([spec])
+        eng.set_pdfs(0, initial_f(spec))
+        x, U, Om = spec.x.copy(), spec.U.copy(), spec.Om.copy()
+        eng.set_particles(0, x, spec.r, U, Om)
+        for _ in range(steps):
+            eng.step(1)
+            xn = np.mod(x + U, L)
+            if split:
+                eng.set_particle_positions(0, xn)
+            F, T = eng.get_forces(0)
+            U = U + F * inv_m
+            Om = Om + T * inv_I
+            if split:
+                eng.set_particle_velocities(0, U, Om)
+            else:
+                eng.set_particles(0, xn, spec.r, U, Om)
+            x = xn
+        results.append((eng.get_pdfs(0).cpu().numpy(), F, T, x, U, Om))
+        with pytest.raises(psm.PsmError) as e:
+            eng.set_particle_velocities(0, U[:-1], Om[:-1])
+        assert e.value.code == psm.PSM_EINVAL
+        eng.close()
+    (fs, Fs, Ts, xs, Us, Oms), (ff, Ff, Tf, *_) = results
+    assert np.array_equal(fs, ff) and np.array_equal(Fs, Ff) and np.array_equal(Ts, Tf)
+    assert_pdfs_close(fs, f, 1e-12)
+    assert_forces_close(Fs, ref.F, ref.A)
+    assert_forces_close(Ts, ref.T, ref.A, lever=spec.r.max() + 1)
+    assert np.allclose(xs, dyn.x, rtol=1e-12, atol=1e-12)
+    assert np.allclose(Us, dyn.U, rtol=1e-12, atol=1e-15)

@@ -312,6 +312,39 @@ def test_autotune_picks_an_allowed_launch_and_keeps_parity():
     eng.close()
 
 
+def test_autotune_cache(tmp_path, monkeypatch):
+    """A second context of the same class (same box, storage, walls and
+    sphere volume fraction) gets the cached pick without trials (its PDF
+    state is left as set); the pick is appended to the file PSM_TUNE_CACHE
+    names; psm_clear_tune_cache forgets it (and does not read the file
+    again), so the next context is timed again."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PSM_TUNE_CACHE", str(cache))
+    psm.psm_clear_tune_cache()
+    spec = inputs.random_small((50, 20, 16), 3, (2.5, 3.5), seed=83, tau=0.7)
+    f0 = initial_f(spec)
+
+    def tuned():
+        eng = make_engine([spec])
+        eng.set_pdfs(0, f0)
+        eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+        shape, ms = eng.autotune(trial_steps=2)
+        advanced = not np.array_equal(eng.get_pdfs(0).cpu().numpy(), f0)
+        eng.close()
+        return shape, ms, advanced
+
+    s1, ms1, adv1 = tuned()
+    s2, ms2, adv2 = tuned()
+    assert adv1 and not adv2 and s1 == s2 and ms1 == ms2
+    lines = cache.read_text().split("\n")
+    assert len([l for l in lines if l.strip()]) == 1 and "|s0|" in lines[0]
+    psm.psm_clear_tune_cache()
+    s3, _, adv3 = tuned()
+    assert adv3
+    monkeypatch.delenv("PSM_TUNE_CACHE")
+    psm.psm_clear_tune_cache()
+
+
 def test_state_and_argument_errors_on_a_live_context():
     """The documented codes on a live context, each leaving it usable: more
     spheres than max_particles (PSM_ECAPACITY), radius out of range, box out

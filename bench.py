@@ -269,6 +269,7 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
     eng.set_equilibrium(0, u0)
     del u0
     x, U, Om = spec.x.copy(), spec.U.copy(), spec.Om.copy()
+    xn, tmp = np.empty_like(x), np.empty_like(x)
     mass = 2.5 * 4.0 / 3.0 * np.pi * spec.r ** 3
     inv_m = (1.0 / mass)[:, None]
     inv_I = (1.0 / (0.4 * mass * spec.r ** 2))[:, None]
@@ -283,7 +284,7 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
     evs = []
 
     def one(record=False):
-        nonlocal x, U, Om
+        nonlocal x, xn
         t0 = time.perf_counter()
         if record:
             e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -292,21 +293,23 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
         if record:
             e[1].record(eng.stream)
         t1 = time.perf_counter()
-        xn = x + U                         # x_{n+1} = x_n + U_n, while the step runs
+        np.add(x, U, out=xn)               # x_{n+1} = x_n + U_n, while the step runs
         np.mod(xn, L, out=xn)
         t2 = time.perf_counter()
-        eng.set_particle_positions(0, xn)
+        eng.set_particle_positions(0, xn)  # copied before the call returns
         if record:
             e[2].record(eng.stream)
         t3 = time.perf_counter()
         F, T = eng.get_forces(0)           # waits for the step
         t4 = time.perf_counter()
-        U += F * inv_m
-        Om += T * inv_I
+        np.multiply(F, inv_m, out=tmp)
+        U += tmp
+        np.multiply(T, inv_I, out=tmp)
+        Om += tmp
         t5 = time.perf_counter()
         eng.set_particle_velocities(0, U, Om)
         t6 = time.perf_counter()
-        x = xn
+        x, xn = xn, x
         if record:
             evs.append(e)
             for k, dt_ in (("step_call", t1 - t0), ("positions", t2 - t1), ("set_positions", t3 - t2),

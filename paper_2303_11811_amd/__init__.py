@@ -211,8 +211,8 @@ def psm_step(ctx, nsteps):
 
 
 def psm_get_forces(ctx, box, n):
-    F = np.zeros((n, 3))
-    T = np.zeros((n, 3))
+    F = np.empty((n, 3))
+    T = np.empty((n, 3))
     _check(lib().psm_get_forces(ctx, box, _dptr(F), _dptr(T)))
     return F, T
 

@@ -265,25 +265,23 @@ __device__ __forceinline__ void pair_fluid(R& fq, R& fb, R cu, const WClass<R>& 
 
 // The same pair under PSM (eqs. 17-19):
 //   f~_q = f_q + (1-B) t_q + B (f_qbar - E_qbar(U) - f_q) + sum_s B_s E_q(V_s),
-//   t_q = omega (E_q(U) - f_q) + F_q = P + A - omega f_q,
+//   t_q = omega (E_q(U) - f_q) + F_q,
 // with the slot sum folded into ten cell scalars:
-//   sum_s B_s E_q(V_s) = W (A0 + k45 c.M.c) + 3 W c.P = sV + aV,
+//   sum_s B_s E_q(V_s) = W (A0 + k45 c.M.c) + 3 W c.P,
 //   A0 = sum_s B_s (rho - k15 V_s.V_s), M = sum_s B_s V_s V_s^T, P = sum_s B_s V_s.
+// Collected by parity in c_q, with alpha = 1 - (1-B) omega - B, beta = (1-B) omega - B
+// and gamma = (1-B) omega + B (per cell):
+//   f~_q    = alpha f_q + B f_qbar + Sym + Anti,  f~_qbar = alpha f_qbar + B f_q + Sym - Anti,
+//   Sym  = [beta W base - (1-B) pu + W A0] + beta W k45 (c.U)^2 + (1-B) fs (c.U) + W k45 c.M.c,
+//   Anti = gamma 3 W (c.U) + (1-B) fa + 3 W c.P,
+// where the bracket (C1), beta W k45 (C2) and gamma 3 W (C3) are per weight class.
 template <class R, int Q>
-__device__ __forceinline__ void pair_psm(R& fq, R& fb, R cu, const WClass<R>& w, R fa, R fs, R omega, R Bt, R omB,
-                                         R WA0, R cM, R cP) {
-    const R cu2 = cu * cu;
-    const R s = fmar(w.Wk, cu2, w.Wb);
-    const R a = w.W3 * cu;
-    const R P = fmar(fs, cu, fmar(w.owk, cu2, w.owb_pu));
-    const R A = fmar(w.ow3, cu, fa);
-    const R sV = fmar(w.Wk, cM, WA0);
-    const R aV = w.W3 * cP;
-    const R D = fb - fq;
-    const R tq = fmar(-omega, fq, P + A);
-    const R tb = fmar(-omega, fb, P - A);
-    const R nq = fmar(omB, tq, fq) + fmar(Bt, (D - s) + a, sV + aV);
-    const R nb = fmar(omB, tb, fb) + fmar(Bt, (-D - s) - a, sV - aV);
+__device__ __forceinline__ void pair_psm(R& fq, R& fb, R cu, R C1, R C2, R C3, R Wk, R W3, R ofs, R ofa, R alpha,
+                                         R Bt, R cM, R cP) {
+    const R Sym = fmar(C2, cu * cu, fmar(ofs, cu, fmar(Wk, cM, C1)));
+    const R Anti = fmar(C3, cu, fmar(W3, cP, ofa));
+    const R nq = fmar(alpha, fq, fmar(Bt, fb, Sym + Anti));
+    const R nb = fmar(alpha, fb, fmar(Bt, fq, Sym - Anti));
     fq = nq;
     fb = nb;
 }
@@ -756,18 +754,21 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S::DEV ? PSM
                     }
                     const R omB = (R)1 - Bt;
                     const R Mxy2 = Mxy + Mxy, Mxz2 = Mxz + Mxz, Myz2 = Myz + Myz;
-                    const R WA01 = (R)W1 * A0, WA02 = (R)W2 * A0;
-                    {
-                        constexpr R w = (R)W0;
-                        const R s0 = w * base;
-                        const R t0 = fmar(omega, s0 - f[0], -pu0);
-                        f[0] = fmar(omB, t0, f[0]) + fmar(-Bt, s0, w * A0);
-                        PSM_STORE(0);
-                    }
-#define PSM_PAIR(Q)                                                                                           \
-    pair_psm<R, Q>(f[Q], f[Q + 1], cdot<R, Q>(Ux, Uy, Uz), Q < 7 ? w1 : w2, PSM_FA(Q), PSM_FS(Q), omega, Bt, omB, \
-                   Q < 7 ? WA01 : WA02, cmc<R, Q>(Mxx, Myy, Mzz, Mxy2, Mxz2, Myz2), cdot<R, Q>(Px, Py, Pz));        \
-    PSM_STORE(Q);                                                                                             \
+                    const R omw = omB * omega;
+                    const R alpha = ((R)1 - Bt) - omw, beta = omw - Bt, gamma = omw + Bt;
+                    const R pu1 = pick<R>(bx.pw[1], bx.pw_f[1]) * Ug3, pu2 = pick<R>(bx.pw[2], bx.pw_f[2]) * Ug3;
+                    const R C11 = fmar(beta, w1.Wb, fmar(-omB, pu1, (R)W1 * A0));
+                    const R C12 = fmar(beta, w2.Wb, fmar(-omB, pu2, (R)W2 * A0));
+                    const R C21 = beta * w1.Wk, C22 = beta * w2.Wk;
+                    const R C31 = gamma * w1.W3, C32 = gamma * w2.W3;
+                    // rest population: c = 0, qbar = q
+                    f[0] = fmar(alpha + Bt, f[0], fmar(beta * (R)W0, base, fmar(-omB, pu0, (R)W0 * A0)));
+                    PSM_STORE(0);
+#define PSM_PAIR(Q)                                                                                              \
+    pair_psm<R, Q>(f[Q], f[Q + 1], cdot<R, Q>(Ux, Uy, Uz), Q < 7 ? C11 : C12, Q < 7 ? C21 : C22, Q < 7 ? C31 : C32, \
+                   Q < 7 ? w1.Wk : w2.Wk, Q < 7 ? w1.W3 : w2.W3, omB * PSM_FS(Q), omB * PSM_FA(Q), alpha, Bt,        \
+                   cmc<R, Q>(Mxx, Myy, Mzz, Mxy2, Mxz2, Myz2), cdot<R, Q>(Px, Py, Pz));                             \
+    PSM_STORE(Q);                                                                                                \
     PSM_STORE(Q + 1)
                     PSM_PAIR(1); PSM_PAIR(3); PSM_PAIR(5); PSM_PAIR(7); PSM_PAIR(9);
                     PSM_PAIR(11); PSM_PAIR(13); PSM_PAIR(15); PSM_PAIR(17);

@@ -175,10 +175,12 @@ int psm_step(psm_ctx* ctx, int nsteps);
  * any step: zeros. */
 int psm_get_forces(psm_ctx* ctx, int box, double* F, double* T);
 
-/* Solid fractions of the current particles (same device mapping as the step):
- * B: device [2][N] FP64, pid: device [2][N] int (box-local particle id, -1 for
- * an empty slot). Slots hold the two largest fractions in ascending id,
- * renormalised to sum 1 where they exceed 1 (Sec. 2.3). */
+/* Solid fractions of the current particles (the mapping of the step, in FP64;
+ * the FP16-deviation step evaluates the linear approximation in FP32, within
+ * about 1e-6 of these): B: device [2][N] FP64, pid: device [2][N] int
+ * (box-local particle id, -1 for an empty slot). Slots hold the two largest
+ * fractions in ascending id, renormalised to sum 1 where they exceed 1
+ * (Sec. 2.3). */
 int psm_get_solid_fraction(psm_ctx* ctx, int box, double* B, int* pid);
 
 /* FP64 totals of the current state of box `box`: mass sum_x sum_q f,

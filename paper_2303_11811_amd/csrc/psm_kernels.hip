@@ -363,7 +363,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S::DEV ? PSM
     // FP32 copies: centre relative to the tile centre (minimum image), the
     // squared reach of the overlap test with a rounding margin, and (for the
     // deviation forms) the velocities
-    __shared__ float s_qx[MAXC], s_qy[MAXC], s_qz[MAXC], s_lim2[MAXC];
+    __shared__ float s_qx[MAXC], s_qy[MAXC], s_qz[MAXC], s_lim2[MAXC], s_rf[MAXC], s_frf[MAXC];
     __shared__ float s_uf[6][MAXC];
     __shared__ int s_pid[MAXC];
     __shared__ double s_acc[NWAVE][6][MAXC];
@@ -428,6 +428,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S::DEV ? PSM
                 s_qz[c] = (float)min_image(pz - tmz, Lz, hLz);
                 const double lim = pr + (lin_map ? pfr : bx.reach) + bx.margin32;
                 s_lim2[c] = (float)(lim * lim);
+                s_rf[c] = (float)pr;
+                s_frf[c] = (float)pfr;
                 const double u[6] = {kp.P.ux[p], kp.P.uy[p], kp.P.uz[p], kp.P.ox[p], kp.P.oy[p], kp.P.oz[p]};
                 s_ux[c] = u[0]; s_uy[c] = u[1]; s_uz[c] = u[2];
                 s_ox[c] = u[3]; s_oy[c] = u[4]; s_oz[c] = u[5];
@@ -510,7 +512,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S::DEV ? PSM
         // Latency hiding: PREF pulls the next cell's 19 values (one cell up in
         // z) while the current one is mapped and collided; EARLY issues the
         // current cell's pulls before its mapping.
-        constexpr bool PREF = S::DEV && (S::SCALED ? PSM_PREFETCH_F16 : PSM_PREFETCH_F32);
+        constexpr bool PREF = S::DEV && !FILT && (S::SCALED ? PSM_PREFETCH_F16 : PSM_PREFETCH_F32);
         constexpr bool EARLY = !PREF && PSM_EARLY_PULLS;
         R fn[NQ];
         if constexpr (PREF) {
@@ -553,9 +555,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S::DEV ? PSM
 
             // 1. solid fractions of this cell from the staged candidates (Sec. 2.3.2);
             // with the filter, only the candidates that can reach this wave at this z.
-            // In the deviation forms an FP32 test with a margin first rejects the
-            // candidates out of reach. The fraction itself is FP64, bit for bit that
-            // of the read-out path.
+            // The fraction is FP64, bit for bit that of the read-out path, except
+            // that the FP16 form takes the linear approximation in FP32.
             int c0 = -1, c1 = -1;
             double B0 = 0.0, B1 = 0.0;
             int dropped = 0;   // overlaps beyond the two slots at this cell
@@ -566,7 +567,15 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S::DEV ? PSM
             const float tx_ = wrap32(rx - s_qx[c], Lxf, iLx);                                               \
             const float ty_ = wrap32(ry - s_qy[c], Lyf, iLy);                                               \
             const float tz_ = wrap32(rz - s_qz[c], Lzf, iLz);                                               \
-            near_ = fmar(tz_, tz_, fmar(ty_, ty_, tx_ * tx_)) <= s_lim2[c];                                 \
+            const float d2_ = fmar(tz_, tz_, fmar(ty_, ty_, tx_ * tx_));                                    \
+            near_ = d2_ <= s_lim2[c];                                                                       \
+            if (S::SCALED && near_ && lin_map) {                                                            \
+                /* FP16 storage: linear approximation of eq. (26) in FP32 (its error, about */              \
+                /* 1e-6 of a cell, is far below the FP16 rounding of the stored values) */                  \
+                const float eps_ = s_frf[c] - (__builtin_amdgcn_sqrtf(d2_) - s_rf[c]);                       \
+                if (eps_ > 0.0f) slots_insert(sl, c, s_pid[c], (double)(eps_ < 1.0f ? eps_ : 1.0f));         \
+                near_ = false;                                                                              \
+            }                                                                                               \
         }                                                                                                   \
         if (near_) {                                                                                        \
             double dx = min_image(cxc - s_px[c], Lx, hLx);                                                  \
@@ -579,6 +588,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S::DEV ? PSM
     } while (0)
             if constexpr (FILT) {
                 unsigned long long cm = nc > 0 ? s_cmask[wave][k] : 0ull;
+                // wave-uniform: keep the mask and its loop in scalar registers
+                cm = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(cm >> 32)) << 32) |
+                     (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)cm);
                 if (cm != 0ull) {
                     Slots sl;
                     slots_init(sl);

@@ -159,3 +159,38 @@ def test_fp16_scale_choice(scale):
     bu, bf = BOUNDS[psm.PSM_FP16DEV]
     assert l2 <= bu and fe <= bf
     eng.close()
+
+
+@pytest.mark.parametrize("dims", [(63, 14, 10), (64, 12, 9), (70, 9, 8)])
+def test_fp16_one_step_every_cell_row_layouts(dims):
+    """Every value of an FP16-deviation box after one step from the engine's
+    own state agrees with the FP64 oracle's step from that state to the
+    one-step bound of psm_cases.deviation_bound. The widths cover the three
+    row layouts of the PDF grid: rows padded to whole 64-cell blocks with an
+    odd and with an even width, and rows packed back to back (a wave's cells
+    then straddle blocks); two tile widths each, with spheres and a body
+    force."""
+    from psm_cases import deviation_bound
+
+    rng = np.random.default_rng(23)
+    x, r = inputs.rsa_spheres(dims, np.array([2.0, 1.5, 1.8]), rng)
+    U = inputs.uniform_velocities(rng, len(r), 0.01)
+    spec = inputs.BoxSpec(dims=dims, tau=0.6, mapping=0, x=x, r=r, U=U, Om=np.zeros_like(U),
+                          u0=inputs.taylor_green(dims, 0.02), fext=(1e-5, 0.0, 0.0))
+    box = oracle.Box(*dims, tau=spec.tau, fext=spec.fext)
+    for launch in ((64, 4, 4, 0), (32, 8, 2, 0)):
+        print(f"[case] fp16 one step dims={dims} launch={launch}", flush=True)
+        eng = make_engine([spec], storage=psm.PSM_FP16DEV, max_radius=2.0)
+        eng.set_launch(*launch)
+        eng.set_pdfs(0, initial_f(spec))
+        eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+        eng.step(3)
+        f_t = eng.get_pdfs(0).cpu().numpy()
+        eng.step(1)
+        got = eng.get_pdfs(0).cpu().numpy()
+        eng.close()
+        ref = oracle.run(box, f_t, 1, x, r, U, spec.Om).f
+        bound = deviation_bound(ref.T, psm.PSM_FP16DEV).T
+        ratio = np.max(np.abs(got - ref) / bound)
+        print(f"[ratio] max |err|/bound = {ratio:.3g}", flush=True)
+        assert np.all(np.abs(got - ref) <= bound), ratio

@@ -112,10 +112,25 @@ def run_case(psm, torch, spec, storage, steps, warmup, autotune, launch=None, fu
     res = dict(ms_per_step=(t1 - t0) * 1e3 / steps, mlups=N * steps / (t1 - t0) / 1e6,
                kernel_ms=kern_ms / max(n_launch, 1), launches=n_launch, launch=list(eng.get_launch()),
                mass=mass, slot_overflows=ov)
+    # the same tiles, pulls and stores with no arithmetic (after the timed
+    # region; the state is not touched): the rate HBM serves this pattern
+    res["pattern_copy_ms"] = {"pull": eng.pattern_copy(1, 10), "own_cell": eng.pattern_copy(0, 10)}
     eng.close()
     del eng
     torch.cuda.empty_cache()
     return res
+
+
+def pattern_summary(res, algo_bytes):
+    """The step kernel against the copy of its own access pattern (same
+    launch, tiles, pulls and stores, no arithmetic): GB/s of the pulled
+    copy, of the copy from each cell's own slots (no shifts), and the
+    kernel's time over the pulled copy's."""
+    pc = res["pattern_copy_ms"]
+    return {"pull_GBps": round(algo_bytes / (pc["pull"] * 1e-3) / 1e9, 1),
+            "own_cell_GBps": round(algo_bytes / (pc["own_cell"] * 1e-3) / 1e9, 1),
+            "pull_ms": round(pc["pull"], 4), "own_cell_ms": round(pc["own_cell"], 4),
+            "kernel_over_pull": round(res["kernel_ms"] / pc["pull"], 4)}
 
 
 def stream_copy_gbps(psm, torch, nbytes=4 << 30, reps=20):
@@ -601,6 +616,7 @@ def main():
             forms[STORAGE_NAME[st]] = {"mlups": r["mlups"], "ms_per_step": r["ms_per_step"], "steps": psteps,
                                        "kernel_ms": r["kernel_ms"], "launch": r["launch"],
                                        "roofline_frac": r["roofline_frac"],
+                                       "pattern_copy": pattern_summary(r, spec.N * BYTES_PER_CELL[st]),
                                        "traffic": traffic, "traffic_launch": traffic_launch,
                                        "speedup_vs_f64": r["mlups"] / main_res["mlups"],
                                        "kernel_speedup_vs_f64": main_res["kernel_ms"] / r["kernel_ms"]}
@@ -686,6 +702,7 @@ def main():
             "kernel": f"k_psm_step<{args.storage}>", "kernel_ms": round(main_res["kernel_ms"], 4),
             "algorithmic_bytes_per_launch": algo_bytes,
             "frac_of_stream_copy": round(achieved / copy_gbps, 4),
+            "pattern_copy": pattern_summary(main_res, algo_bytes),
         },
         "cpu_baseline": cpu,
         "stream_copy_GBps": round(copy_gbps, 1),

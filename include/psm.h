@@ -315,6 +315,18 @@ int psm_field_stats_noalloc(const double* f, long long ncells, double* out, void
  * streaming copy kernel. */
 int psm_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
 
+/* Bandwidth reference at the step's own access pattern (eq. 28 prices the
+ * step by its PDF bytes; this measures the rate HBM serves those bytes in the
+ * step's order): nrep launches of a kernel that walks every tile of every box
+ * at the current launch shape and grid, pulls the 19 stored values of each
+ * cell as psm_step does (shifted = 1: from x - c_q) or from the cell itself
+ * (shifted = 0), and stores them unchanged at the cell in the grid psm_step
+ * writes next, with no other arithmetic. The state psm_step reads is not
+ * touched, so stepping may continue afterwards. Synchronises the context's
+ * stream; *ms receives the average time of one launch (HIP events).
+ * PSM_EINVAL for shifted other than 0/1, nrep < 1 or a NULL ms. */
+int psm_pattern_copy(psm_ctx* ctx, int shifted, int nrep, double* ms);
+
 /* Text of the last error on this thread ("" if none). Never NULL. */
 const char* psm_last_error(void);
 

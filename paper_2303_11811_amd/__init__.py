@@ -76,6 +76,7 @@ _SIGS = {
     "psm_set_timing": ([_P, ctypes.c_int], ctypes.c_int),
     "psm_get_timing": ([_P, ctypes.POINTER(ctypes.c_longlong), _D], ctypes.c_int),
     "psm_reset_timing": ([_P], ctypes.c_int),
+    "psm_pattern_copy": ([_P, ctypes.c_int, ctypes.c_int, _D], ctypes.c_int),
     "psm_set_dynamics": ([_P, ctypes.c_int, ctypes.c_double, _D], ctypes.c_int),
     "psm_integrate": ([_P, ctypes.c_double, ctypes.c_int], ctypes.c_int),
     "psm_get_particles": ([_P, ctypes.c_int, _D, _D, _D], ctypes.c_int),
@@ -286,6 +287,12 @@ def psm_set_timing(ctx, enable):
     return _check(lib().psm_set_timing(ctx, int(bool(enable))))
 
 
+def psm_pattern_copy(ctx, shifted, nrep):
+    ms = ctypes.c_double(0)
+    _check(lib().psm_pattern_copy(ctx, int(shifted), int(nrep), ctypes.byref(ms)))
+    return ms.value
+
+
 def psm_get_timing(ctx):
     n = ctypes.c_longlong(0)
     ms = ctypes.c_double(0)
@@ -464,6 +471,10 @@ class Engine:
 
     def reset_timing(self):
         psm_reset_timing(self.ctx)
+
+    def pattern_copy(self, shifted, nrep):
+        """Average ms of one access-pattern copy launch (psm_pattern_copy)."""
+        return psm_pattern_copy(self.ctx, shifted, nrep)
 
     def synchronize(self):
         self.stream.synchronize()

@@ -1193,6 +1193,30 @@ extern "C" int psm_get_timing(psm_ctx* c, long long* launches, double* total_ms)
     return PSM_OK;
 }
 
+extern "C" int psm_pattern_copy(psm_ctx* c, int shifted, int nrep, double* ms) {
+    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    if (shifted != 0 && shifted != 1) return fail(PSM_EINVAL, "shifted must be 0 or 1");
+    if (nrep < 1) return fail(PSM_EINVAL, "nrep < 1");
+    if (!ms) return fail(PSM_EINVAL, "ms is NULL");
+    StepParams kp;
+    step_params(c, c->parity, kp);
+    hipEvent_t e[2] = {nullptr, nullptr};
+    HIP_TRY(hipEventCreate(&e[0]));
+    hipError_t err = hipEventCreate(&e[1]);
+    if (err == hipSuccess) err = hipEventRecord(e[0], c->stream);
+    for (int i = 0; i < nrep && err == hipSuccess; ++i)
+        err = launch_pattern_copy(c->storage, shifted != 0, kp, c->grid, c->stream);
+    if (err == hipSuccess) err = hipEventRecord(e[1], c->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e[1]);
+    float t = 0.0f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e[0], e[1]);
+    (void)hipEventDestroy(e[0]);
+    if (e[1]) (void)hipEventDestroy(e[1]);
+    if (err != hipSuccess) return fail(PSM_EHIP, "psm_pattern_copy: %s", hipGetErrorString(err));
+    *ms = (double)t / nrep;
+    return PSM_OK;
+}
+
 extern "C" int psm_reset_timing(psm_ctx* c) {
     if (!c) return fail(PSM_EINVAL, "ctx is NULL");
     HIP_TRY(hipStreamSynchronize(c->stream));

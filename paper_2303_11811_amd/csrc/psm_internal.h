@@ -302,6 +302,7 @@ struct IntParams {
 };
 
 hipError_t launch_step(int storage, int map, bool filt, const StepParams& kp, int grid, hipStream_t st);
+hipError_t launch_pattern_copy(int storage, bool shifted, const StepParams& kp, int grid, hipStream_t st);
 int step_blocks_per_cu(int storage, int map, bool filt);
 hipError_t launch_reduce(const ReduceParams& rp, hipStream_t st);
 int scan_chunks(int n);

@@ -1474,6 +1474,86 @@ static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + 
 // The step kernel instance for (storage, map, filt): storage psm_storage;
 // map 0 when every box uses the linear approximation, 1 if any box samples;
 // filt the per-wave candidate filter.
+// ---------------------------------------------------------------------------
+// Bandwidth reference for the step's access pattern: the tile walk, pulls and
+// stores of k_psm_step with no arithmetic. SHIFT pulls each direction from
+// x - c_q on the source planes z, z -+ 1 as the step does; otherwise every
+// direction comes from the cell itself. Values are stored unchanged at the
+// cell in the other grid (the source grid is not written).
+template <class S, bool SHIFT>
+__global__ __launch_bounds__(WG) void k_pattern_copy(StepParams kp) {
+    using R = typename S::R;
+    using T = typename S::T;
+    const int tid = threadIdx.x;
+    const int TX = kp.tx, TY = kp.ty, TZ = kp.tz;
+    const int lx = tid % TX, ly = tid / TX;
+    const int G = gridDim.x;
+    const int xcd = blockIdx.x % NXCD;
+    const int gx8 = (G - xcd + NXCD - 1) / NXCD;
+    const int t_begin = (int)(((long long)kp.T_total * xcd) / NXCD);
+    const int t_end = (int)(((long long)kp.T_total * (xcd + 1)) / NXCD);
+    const PSM_CONST BoxDev* boxes = cptr(kp.boxes);
+    for (int t = t_begin + (int)blockIdx.x / NXCD; t < t_end; t += gx8) {
+        int b = 0;
+        if (kp.nbox > 1) {
+            const PSM_CONST int* tb = cptr(kp.box_tile_base);
+            int lo = 0, hi = kp.nbox - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (tb[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            b = lo;
+        }
+        const PSM_CONST BoxDev& bx = boxes[b];
+        const int nx = bx.nx, ny = bx.ny, nz = bx.nz;
+        const int lt = t - bx.tile_base;
+        const int tcx = lt % bx.ntx, tcy = (lt / bx.ntx) % bx.nty, tcz = lt / (bx.ntx * bx.nty);
+        const int x = tcx * TX + lx, y = tcy * TY + ly;
+        if (x >= nx || y >= ny) continue;
+        const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+        const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+        const int pitch = bx.pitch;
+        auto inplane = [pitch](int xx, int yy) -> unsigned {
+            int c = xx + pitch * yy;
+            return (unsigned)(((c / BLK) * (NQ * BLK) + (c % BLK)) * (int)sizeof(T));
+        };
+        const unsigned o00 = inplane(x, y);
+        const unsigned om0 = SHIFT ? inplane(xm, y) : o00, op0 = SHIFT ? inplane(xp, y) : o00;
+        const unsigned o0m = SHIFT ? inplane(x, ym) : o00, o0p = SHIFT ? inplane(x, yp) : o00;
+        const unsigned omm = SHIFT ? inplane(xm, ym) : o00, opp = SHIFT ? inplane(xp, yp) : o00;
+        const unsigned omp = SHIFT ? inplane(xm, yp) : o00, opm = SHIFT ? inplane(xp, ym) : o00;
+        const long long pbytes = bx.plane_elems * (long long)sizeof(T);
+        const unsigned pb32 = (unsigned)pbytes;
+        const char* src = (const char*)bx.grid[kp.parity];
+        const char* dst = (const char*)bx.grid[kp.parity ^ 1];
+        constexpr int QB = BLK * (int)sizeof(T);
+        for (int k = 0; k < TZ; ++k) {
+            const int z = tcz * TZ + k;
+            if (z >= nz) break;
+            const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+            const Rsrc sz = plane_rsrc(src + z * pbytes, pb32);
+            const Rsrc sm = SHIFT ? plane_rsrc(src + zm * pbytes, pb32) : sz;
+            const Rsrc sp = SHIFT ? plane_rsrc(src + zp * pbytes, pb32) : sz;
+            const Rsrc dz_ = plane_rsrc(dst + z * pbytes, pb32);
+            R f[NQ];
+            PSM_LOAD19(f, sz, sm, sp);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) S::st(dz_, o00, q * QB, f[q]);
+        }
+    }
+}
+
+hipError_t launch_pattern_copy(int storage, bool shifted, const StepParams& kp, int grid, hipStream_t st) {
+    const void* k;
+    switch (storage) {
+        case 0: k = shifted ? (const void*)k_pattern_copy<St64, true> : (const void*)k_pattern_copy<St64, false>; break;
+        case 1: k = shifted ? (const void*)k_pattern_copy<St32, true> : (const void*)k_pattern_copy<St32, false>; break;
+        default: k = shifted ? (const void*)k_pattern_copy<St16, true> : (const void*)k_pattern_copy<St16, false>;
+    }
+    void* args[] = {(void*)&kp};
+    return hipLaunchKernel(k, dim3(grid), dim3(WG), args, 0, st);
+}
+
 template <int MAP, bool FILT>
 static const void* step_kernel_of(int storage) {
     switch (storage) {

@@ -91,6 +91,8 @@ def test_null_context_calls():
 def test_stream_copy_argument_checks():
     L = psm.lib()
     assert L.psm_stream_copy(None, None, 16, None) == psm.PSM_EINVAL
+    ms = ctypes.c_double(0)
+    assert L.psm_pattern_copy(None, 1, 1, ctypes.byref(ms)) == psm.PSM_EINVAL
     assert L.psm_stream_copy(ctypes.c_void_p(256), ctypes.c_void_p(4096), 15, None) == psm.PSM_EINVAL
     assert L.psm_stream_copy(ctypes.c_void_p(256), ctypes.c_void_p(264), 64, None) == psm.PSM_EINVAL
 

@@ -259,6 +259,32 @@ def test_checkpoint_resume_bitwise():
     assert np.array_equal(F_full, F_res) and np.array_equal(T_full, T_res)
 
 
+@pytest.mark.parametrize("storage", [psm.PSM_FP64, psm.PSM_FP16DEV])
+def test_pattern_copy_leaves_the_state(storage):
+    """The access-pattern bandwidth reference writes only the grid the next
+    step overwrites: the state, and the steps after it, are bit for bit those
+    of a context that never ran it."""
+    spec = inputs.random_small((44, 36, 30), 5, (3.0, 4.5), seed=92, tau=0.62, fext=(1e-5, 0, 0))
+    f_ref, F_ref, T_ref, *_ = run_engine(spec, 4, storage=storage, launch=(64, 4, 2, 0))
+    eng = make_engine([spec], storage=storage)
+    eng.set_launch(64, 4, 2, 0)
+    eng.set_pdfs(0, initial_f(spec))
+    eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+    eng.step(2)
+    f_mid = eng.get_pdfs(0).cpu().numpy()
+    for shifted in (1, 0):
+        ms = eng.pattern_copy(shifted, 2)
+        assert ms > 0.0
+    assert np.array_equal(eng.get_pdfs(0).cpu().numpy(), f_mid)
+    eng.step(2)
+    F, T = eng.get_forces(0)
+    assert np.array_equal(eng.get_pdfs(0).cpu().numpy(), f_ref)
+    assert np.array_equal(F, F_ref) and np.array_equal(T, T_ref)
+    with pytest.raises(psm.PsmError):
+        eng.pattern_copy(2, 1)
+    eng.close()
+
+
 def test_nonfinite_state_is_reported():
     spec = inputs.random_small((24, 20, 16), 2, (2.5, 3.0), seed=5, tau=0.7)
     f0 = initial_f(spec)

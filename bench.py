@@ -318,9 +318,9 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
         F, T = eng.get_forces(0)           # waits for the step
         t4 = time.perf_counter()
         np.multiply(F, inv_m, out=tmp)
-        U += tmp
+        np.add(U, tmp, out=U)
         np.multiply(T, inv_I, out=tmp)
-        Om += tmp
+        np.add(Om, tmp, out=Om)
         t5 = time.perf_counter()
         eng.set_particle_velocities(0, U, Om)
         t6 = time.perf_counter()

@@ -284,11 +284,12 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
     eng.set_equilibrium(0, u0)
     del u0
     x, U, Om = spec.x.copy(), spec.U.copy(), spec.Om.copy()
-    xn, tmp = np.empty_like(x), np.empty_like(x)
+    xn, F, T = np.empty_like(x), np.empty_like(x), np.empty_like(x)
     mass = 2.5 * 4.0 / 3.0 * np.pi * spec.r ** 3
-    inv_m = (1.0 / mass)[:, None]
-    inv_I = (1.0 / (0.4 * mass * spec.r ** 2))[:, None]
-    L = np.asarray(spec.dims, dtype=np.float64)
+    inv_m = np.repeat((1.0 / mass)[:, None], 3, axis=1)
+    inv_I = np.repeat((1.0 / (0.4 * mass * spec.r ** 2))[:, None], 3, axis=1)
+    L = float(spec.dims[0])
+    assert spec.dims[0] == spec.dims[1] == spec.dims[2]
     eng.set_particles(0, x, spec.r, U, Om)
 
     # per-module record of the host loop: host times around each call, and
@@ -309,18 +310,19 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
             e[1].record(eng.stream)
         t1 = time.perf_counter()
         np.add(x, U, out=xn)               # x_{n+1} = x_n + U_n, while the step runs
-        np.mod(xn, L, out=xn)
+        xn[xn >= L] -= L                   # |U| < 1: one period at most
+        xn[xn < 0.0] += L
         t2 = time.perf_counter()
         eng.set_particle_positions(0, xn)  # copied before the call returns
         if record:
             e[2].record(eng.stream)
         t3 = time.perf_counter()
-        F, T = eng.get_forces(0)           # waits for the step
+        eng.get_forces(0, F, T)            # waits for the step
         t4 = time.perf_counter()
-        np.multiply(F, inv_m, out=tmp)
-        np.add(U, tmp, out=U)
-        np.multiply(T, inv_I, out=tmp)
-        np.add(Om, tmp, out=Om)
+        np.multiply(F, inv_m, out=F)       # U_{n+1} = U_n + F_n / m
+        np.add(U, F, out=U)
+        np.multiply(T, inv_I, out=T)       # Omega_{n+1} = Omega_n + T_n / I
+        np.add(Om, T, out=Om)
         t5 = time.perf_counter()
         eng.set_particle_velocities(0, U, Om)
         t6 = time.perf_counter()

@@ -211,9 +211,14 @@ def psm_step(ctx, nsteps):
     return _check(lib().psm_step(ctx, int(nsteps)))
 
 
-def psm_get_forces(ctx, box, n):
-    F = np.empty((n, 3))
-    T = np.empty((n, 3))
+def psm_get_forces(ctx, box, n, F=None, T=None):
+    """F, T (n, 3) FP64; caller arrays of that shape (C-contiguous FP64) are
+    filled in place when given."""
+    F = np.empty((n, 3)) if F is None else F
+    T = np.empty((n, 3)) if T is None else T
+    for a in (F, T):
+        if a.shape != (n, 3) or a.dtype != np.float64 or not a.flags.c_contiguous:
+            raise ValueError(f"force arrays must be C-contiguous float64 of shape ({n}, 3)")
     _check(lib().psm_get_forces(ctx, box, _dptr(F), _dptr(T)))
     return F, T
 
@@ -420,8 +425,8 @@ class Engine:
     def step(self, n=1):
         psm_step(self.ctx, n)
 
-    def get_forces(self, box=0):
-        return psm_get_forces(self.ctx, box, self.np[box])
+    def get_forces(self, box=0, F=None, T=None):
+        return psm_get_forces(self.ctx, box, self.np[box], F, T)
 
     def set_dynamics(self, box, density_ratio, accel=None):
         psm_set_dynamics(self.ctx, box, density_ratio, accel)

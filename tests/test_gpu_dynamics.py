@@ -195,12 +195,18 @@ def test_host_coupling_with_split_updates_matches_oracle():
         eng.set_pdfs(0, initial_f(spec))
         x, U, Om = spec.x.copy(), spec.U.copy(), spec.Om.copy()
         eng.set_particles(0, x, spec.r, U, Om)
+        Fb, Tb = np.empty_like(x), np.empty_like(x)
         for _ in range(steps):
             eng.step(1)
             xn = np.mod(x + U, L)
             if split:
                 eng.set_particle_positions(0, xn)
-            F, T = eng.get_forces(0)
+                # the caller's arrays, filled in place
+                F, T = eng.get_forces(0, Fb, Tb)
+                assert F is Fb and T is Tb
+                F, T = F.copy(), T.copy()
+            else:
+                F, T = eng.get_forces(0)
             U = U + F * inv_m
             Om = Om + T * inv_I
             if split:

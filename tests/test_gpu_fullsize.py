@@ -1,6 +1,6 @@
 """Full-size check of the benchmark workload: 512^3 periodic box, FP64,
 tau 0.55, body force 1e-6, 3204 spheres of diameter 20, in the launch shape
-the autotuner picks (as bench.py does).
+bench.py times (that of the committed counter run, else the autotuner's).
 
 The oracle cannot run 1.3e8 cells, so it checks what it can compute one by
 one from the engine's own state at step t:
@@ -18,6 +18,7 @@ import pytest
 import oracle
 import paper_2303_11811_amd as psm
 from paper_2303_11811_amd import inputs
+from psm_cases import bench_launch
 
 pytestmark = pytest.mark.gpu
 
@@ -36,8 +37,13 @@ def fullsize():
     with torch.cuda.stream(eng.stream):
         u0 = torch.zeros((3, spec.N), dtype=torch.float64, device=eng.device)
     eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
-    eng.set_equilibrium(0, u0)
-    eng.autotune(trial_steps=2)
+    launch = bench_launch(psm.PSM_FP64)
+    if launch is None:
+        eng.set_equilibrium(0, u0)
+        eng.autotune(trial_steps=2)
+    else:
+        eng.set_launch(*launch)
+    print(f"[case] launch {eng.get_launch()}", flush=True)
     eng.set_equilibrium(0, u0)
     del u0
     eng.step(5)

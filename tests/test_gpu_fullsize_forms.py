@@ -1,7 +1,7 @@
-"""Full-size checks of the other benchmark workloads, in the launch the
-autotuner picks (as bench.py does): the FP32- and FP16-deviation forms at
-512^3, the 64 batched boxes, and the 768^3 dense suspension after device-side
-particle updates. The oracle computes sampled cells one by one from the
+"""Full-size checks of the other benchmark workloads, in the launch bench.py
+times (for the 512^3 forms that of the committed counter run, else the
+autotuner's): the FP32- and FP16-deviation forms at 512^3, the 64 batched
+boxes, and the 768^3 dense suspension after device-side particle updates. The oracle computes sampled cells one by one from the
 engine's own state at step t (FP64, all spheres brute force) and the engine's
 f(t+1) must agree to the bound of one FP32 step with the storage rounding
 (psm_cases.deviation_bound); sampled sphere forces agree to 1e-6 of the sum of
@@ -12,7 +12,7 @@ import pytest
 import oracle
 import paper_2303_11811_amd as psm
 from paper_2303_11811_amd import inputs
-from psm_cases import deviation_bound, gather_sources, one_step_sampled, oracle_after, sample_cells
+from psm_cases import bench_launch, deviation_bound, gather_sources, one_step_sampled, oracle_after, sample_cells
 
 pytestmark = pytest.mark.gpu
 
@@ -70,8 +70,13 @@ def test_precision_form_512_sampled(storage):
     eng = psm.Engine([psm.desc_from_spec(spec)], storage=storage)
     u0 = _u0(eng, spec, torch)
     eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
-    eng.set_equilibrium(0, u0)
-    eng.autotune(trial_steps=2)
+    launch = bench_launch(storage)
+    if launch is None:
+        eng.set_equilibrium(0, u0)
+        eng.autotune(trial_steps=2)
+    else:
+        eng.set_launch(*launch)
+    print(f"[case] launch {eng.get_launch()}", flush=True)
     eng.set_equilibrium(0, u0)
     del u0
     eng.step(5)

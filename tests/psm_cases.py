@@ -156,3 +156,48 @@ def bench_launch(storage):
     _, launch = bench.measured_traffic(storage)
     return tuple(launch) if launch else None
 
+
+def post_collision_field(box, f, x, r, U, Om):
+    """The oracle's post-collision values f~ [19][N] of every cell of state f
+    (its own slots and collision, cell by cell)."""
+    B, pid, _ = oracle.solid_map(box, x, r) if len(r) else (np.zeros((2, box.N)), -np.ones((2, box.N), int), 0)
+    ft = np.empty_like(f)
+    nx, ny = box.nx, box.ny
+    for n in range(box.N):
+        i, j, k = n % nx, (n // nx) % ny, n // (nx * ny)
+        ns = int((pid[:, n] >= 0).sum())
+        ft[:, n], _ = oracle.collide_cell(box, i, j, k, f[:, n], pid[:ns, n], B[:ns, n], x, U, Om)
+    return ft
+
+
+def one_step_bound(spec, storage, f_t, ft):
+    """Per-value bound [19][N] for one step of a deviation form from the
+    canonical state f_t, with ft the oracle's post-collision field of f_t.
+    Each canonical value after the step comes from one stored post-collision
+    value: f~_q(x - c_q) for a plain pull, f~_qbar(x) for a population that
+    enters through a wall or face (the wall or face term is added exactly on
+    read-out). The bound is the storage rounding of that stored value (FP32:
+    2^-24 relative; FP16 keeps 2^10 d: 2^-11 relative, 2^-35 absolute below
+    the normal range) plus sixteen FP32 roundings at the largest deviation
+    of the computing cell before or after its collision (16 x 2^-24 < 1e-6)."""
+    nx, ny, nz = spec.dims
+    n = np.arange(nx * ny * nz)
+    i, j, k = n % nx, (n // nx) % ny, n // (nx * ny)
+    dt = np.abs(ft - W[:, None])
+    scale = np.maximum(dt.max(axis=0), np.abs(f_t - W[:, None]).max(axis=0))
+    walled = (getattr(spec, "walls_x", False), getattr(spec, "walls_y", False), getattr(spec, "walls_z", False))
+    out = np.empty_like(ft)
+    opp = np.array([0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17])
+    for q in range(19):
+        si, sj, sk = i - CX[q], j - CY[q], k - CZ[q]
+        through = np.zeros(len(n), bool)
+        for a, (sv, L) in enumerate(((si, nx), (sj, ny), (sk, nz))):
+            if walled[a]:
+                through |= (sv < 0) | (sv >= L)
+        src = (si % nx) + nx * ((sj % ny) + ny * (sk % nz))
+        d_src = np.where(through, dt[opp[q], n], dt[q, src])
+        c_src = np.where(through, scale[n], scale[src])
+        rel, ab = (2.0 ** -11, 2.0 ** -35) if storage == psm.PSM_FP16DEV else (2.0 ** -24, 0.0)
+        out[q] = rel * d_src + ab + 1e-6 * c_src
+    return out
+

@@ -361,3 +361,37 @@ def test_mixed_boxes_deviation_forms_with_graphs(storage, tol_u):
         _, u_ref = oracle.macroscopic(ob, f)
         _, u = oracle.macroscopic(ob, got[b])
         assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < tol_u, b
+
+
+@pytest.mark.parametrize("storage", [psm.PSM_FP32DEV, psm.PSM_FP16DEV])
+@pytest.mark.parametrize("case", ["moving_walls", "bed"])
+def test_deviation_forms_one_step_every_value_with_boundaries(storage, case):
+    """Every value of the box after one step from the engine's own state
+    agrees with the FP64 oracle's step from that state to the one-step bound
+    of the deviation forms (psm_cases.one_step_bound: the storage rounding of
+    the stored post-collision value each canonical value comes from, which
+    for a population entering through a wall or face is the cell's own
+    opposite value, plus the FP32 collision): moving no-slip walls with a
+    body force, and the bed box (resting side walls, velocity inflow, pressure
+    outflow at a raised density), two launches each."""
+    from psm_cases import one_step_bound, oracle_box, post_collision_field
+
+    spec = (_channel((34, 22, 20), 3, seed=31) if case == "moving_walls"
+            else _bed((30, 22, 24), 3, seed=32, rho_out=1.002))
+    box = oracle_box(spec)
+    for launch in ((64, 4, 4, 0), (32, 8, 2, 0)):
+        print(f"[case] one step {case} storage={storage} launch={launch}", flush=True)
+        eng = make_engine([spec], storage=storage)
+        eng.set_launch(*launch)
+        eng.set_pdfs(0, initial_f(spec))
+        eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+        eng.step(3)
+        f_t = eng.get_pdfs(0).cpu().numpy()
+        eng.step(1)
+        got = eng.get_pdfs(0).cpu().numpy()
+        eng.close()
+        ref = oracle.run(box, f_t, 1, spec.x, spec.r, spec.U, spec.Om).f
+        bound = one_step_bound(spec, storage, f_t, post_collision_field(box, f_t, spec.x, spec.r, spec.U, spec.Om))
+        ratio = float(np.max(np.abs(got - ref) / bound))
+        print(f"[ratio] max |err|/bound = {ratio:.3g}", flush=True)
+        assert ratio <= 1.0

@@ -100,18 +100,27 @@ def run_case(psm, torch, spec, storage, steps, warmup, autotune, launch=None, fu
     eng.reset_timing()
     eng.set_timing(True)
     torch.cuda.synchronize()
+    # five consecutive windows of the timed steps (each step of the full loop
+    # ends in a synchronising force read, so the marks need no extra sync)
+    nwin = 5 if full_loop and steps >= 50 else 1
+    edges = [steps * w // nwin for w in range(nwin + 1)]
+    marks = []
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
+        if i in edges:
+            marks.append(time.perf_counter())
         one_step()
     eng.synchronize()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    marks.append(t1)
     n_launch, kern_ms = eng.get_timing()
     eng.set_timing(False)
     mass, mom, ov = eng.get_stats(0)
+    win = [N * (edges[w + 1] - edges[w]) / (marks[w + 1] - marks[w]) / 1e6 for w in range(nwin)]
     res = dict(ms_per_step=(t1 - t0) * 1e3 / steps, mlups=N * steps / (t1 - t0) / 1e6,
                kernel_ms=kern_ms / max(n_launch, 1), launches=n_launch, launch=list(eng.get_launch()),
-               mass=mass, slot_overflows=ov)
+               mass=mass, slot_overflows=ov, window_mlups=[round(v, 1) for v in win])
     # the same tiles, pulls and stores with no arithmetic (after the timed
     # region; the state is not touched): the rate HBM serves this pattern
     res["pattern_copy_ms"] = {"pull": eng.pattern_copy(1, 10), "own_cell": eng.pattern_copy(0, 10)}
@@ -709,6 +718,8 @@ def main():
         "cpu_baseline": cpu,
         "stream_copy_GBps": round(copy_gbps, 1),
         "mlups_frac_of_stream_copy": round(main_res["mlups"] * 1e6 * BYTES_PER_CELL[main_st] / 1e9 / copy_gbps, 4),
+        "window_mlups": main_res["window_mlups"],
+        "window_mlups_median": round(float(sorted(main_res["window_mlups"])[len(main_res["window_mlups"]) // 2]), 1),
         "precision_forms": forms,
         "other_workloads": extra,
     }

@@ -158,7 +158,8 @@ def test_bench_host_loops_run_against_a_stub_engine():
 
     fpsm, ftorch = _stub_modules()
     spec = inputs.paper_scale(n=48, seed=1)
-    r = bench.run_case(fpsm, ftorch, spec, 0, 3, 1, True)
+    r = bench.run_case(fpsm, ftorch, spec, 0, 60, 1, True)
+    assert len(r["window_mlups"]) == 5
     s = bench.pattern_summary(r, spec.N * bench.BYTES_PER_CELL[0])
     assert s["kernel_over_pull"] == 1.0 and r["launch"] == [64, 4, 1, 0]
     b = bench.run_batched(fpsm, ftorch, inputs, steps=3, nbox=2)

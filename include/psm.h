@@ -251,8 +251,10 @@ int psm_get_particles(psm_ctx* ctx, int box, double* x, double* U, double* omega
 
 /* Launch options of the step kernel (bit flags). */
 enum psm_launch_flags {
-    PSM_LAUNCH_PERSISTENT = 1,  /* grid sized to the workgroups that fit on the chip at once, each
-                                   walking a contiguous share of the tiles (else one workgroup per tile) */
+    PSM_LAUNCH_PERSISTENT = 1,  /* grid sized to the workgroups that fit on the chip at once; the
+                                   workgroups on each of the 8 dies take the next tile of that die's
+                                   eighth of the tile list from a counter the library zeroes before
+                                   every step (else one workgroup per tile); same results bit for bit */
     PSM_LAUNCH_FILTER = 2       /* per wave and z, test each staged sphere against the rectangle of
                                    the wave's cells first; the per-cell mapping of Sec. 2.3.2 then
                                    visits only spheres that can reach them (same results) */

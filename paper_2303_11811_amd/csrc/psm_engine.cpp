@@ -219,7 +219,8 @@ struct psm_ctx {
     Particles P{};
     int *d_tcnt = nullptr, *d_toff = nullptr, *d_tpid = nullptr;
     double* d_partial = nullptr;
-    int* d_misc = nullptr;               // [0..1] bin stats, [8..9] dropped (u64), [16] device error word
+    int* d_misc = nullptr;               // [0..1] bin stats, [8..9] dropped (u64), [16] device error word,
+                                         // [32..39] tile counters of the persistent grid
     int* d_flags = nullptr;              // d_misc + 16 (FLAG_* bits)
     int* h_flags = nullptr;              // pinned copy of the device error word
     double* d_statpart = nullptr;
@@ -833,6 +834,7 @@ static int step_params(psm_ctx* c, int parity, StepParams& kp) {
     kp.h_scale = c->h_scale;
     kp.h_inv = c->h_inv;
     kp.flags = c->d_flags;
+    kp.queue = c->ts.persistent ? c->d_misc + 32 : nullptr;   // ints 32..39 of the counter block
     return PSM_OK;
 }
 
@@ -868,6 +870,9 @@ static int enqueue_step(psm_ctx* c, bool timed) {
         e1 = next_event(c);
         if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
     }
+    // the persistent grid's tile counters start at zero (a kernel, not a
+    // memset: the step may be captured into a graph)
+    if (kp.queue) HIP_TRY(launch_fill_int(kp.queue, NXCD, 0, c->stream));
     HIP_TRY(launch_step(c->storage, c->map_mode, c->ts.filter != 0, kp, c->grid, c->stream));
     if (timed && e1) HIP_TRY(hipEventRecord(e1, c->stream));
     HIP_TRY(launch_reduce(reduce_params(c), c->stream));

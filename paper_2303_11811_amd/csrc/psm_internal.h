@@ -264,6 +264,7 @@ struct StepParams {
     int parity;
     float h_scale, h_inv;       // FP16 storage scale and its inverse (1 otherwise)
     int* flags;                 // device error word: |= FLAG_SLOT_OVERFLOW when a cell meets a third sphere
+    int* queue;                 // [NXCD] tile counters of the persistent grid (zeroed before the launch), or null
 };
 
 struct ReduceParams {

@@ -388,7 +388,18 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S::DEV ? PSM
     const PSM_CONST BoxDev* boxes = cptr(kp.boxes);
     const PSM_CONST int* tile_off = cptr(kp.tile_off);
 
-    for (int t = t_begin + m; t < t_end; t += gx8) {
+    // Tile order: with a queue (persistent grid), the workgroups of a die take
+    // the next tile of its eighth from that die's counter as they finish one;
+    // otherwise workgroup m of a die takes tiles m, m + gx8, ...
+    __shared__ int s_next;
+    int* const queue = kp.queue;
+    int t = t_begin + m;
+    if (queue) {
+        if (tid == 0) s_next = t_begin + atomicAdd(queue + xcd, 1);
+        __syncthreads();
+        t = s_next;
+    }
+    while (t < t_end) {
         int b = 0;
         if (kp.nbox > 1) {
             const PSM_CONST int* tb = cptr(kp.box_tile_base);
@@ -848,6 +859,14 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S::DEV ? PSM
             }
         }
         __syncthreads();
+        // every thread has read s_next before the barriers of this tile
+        if (queue) {
+            if (tid == 0) s_next = t_begin + atomicAdd(queue + xcd, 1);
+            __syncthreads();
+            t = s_next;
+        } else {
+            t += gx8;
+        }
     }
 }
 

@@ -260,6 +260,33 @@ def test_checkpoint_resume_bitwise():
 
 
 @pytest.mark.parametrize("storage", [psm.PSM_FP64, psm.PSM_FP16DEV])
+def test_persistent_grid_matches_one_workgroup_per_tile(storage):
+    """The persistent grid hands tiles out through per-die counters that a
+    kernel zeroes before every step, also inside captured graphs: its PDFs,
+    forces and torques are bit for bit those of one workgroup per tile at the
+    same tile shape, over eager steps and over several graph replays."""
+    specs = [inputs.random_small((44, 36, 30), 5, (3.0, 4.5), seed=93, tau=0.62, fext=(1e-5, 0, 0)),
+             inputs.random_small((21, 50, 17), 3, (2.5, 3.5), seed=94, tau=0.8)]
+    out = {}
+    for flags in (0, psm.PSM_LAUNCH_PERSISTENT):
+        eng = make_engine(specs, storage=storage, max_radius=4.5)
+        eng.set_launch(64, 4, 2, flags)
+        for b, sp in enumerate(specs):
+            eng.set_pdfs(b, initial_f(sp))
+            eng.set_particles(b, sp.x, sp.r, sp.U, sp.Om)
+        res = []
+        for graph, n in ((False, 3), (True, 10), (True, 10), (False, 1), (True, 10)):
+            eng.set_graph(graph)
+            eng.step(n)
+            res.append([(eng.get_pdfs(b).cpu().numpy(), *eng.get_forces(b)) for b in range(len(specs))])
+        out[flags] = res
+        eng.close()
+    for r0, r1 in zip(out[0], out[psm.PSM_LAUNCH_PERSISTENT]):
+        for a, b in zip(r0, r1):
+            assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("storage", [psm.PSM_FP64, psm.PSM_FP16DEV])
 def test_pattern_copy_leaves_the_state(storage):
     """The access-pattern bandwidth reference writes only the grid the next
     step overwrites: the state, and the steps after it, are bit for bit those

@@ -549,7 +549,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--launch", type=str, default=None, help="tx,ty,tz,flags (skips the autotuner)")
     ap.add_argument("--no-autotune", action="store_true")

@@ -17,6 +17,7 @@ the 8 TB/s HBM peak. `cpu_baseline` is the FP64 oracle (single thread) on a
 bounded sample of the same workload.
 """
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -100,6 +101,9 @@ def run_case(psm, torch, spec, storage, steps, warmup, autotune, launch=None, fu
     eng.reset_timing()
     eng.set_timing(True)
     torch.cuda.synchronize()
+    # no Python garbage collection inside the timed loop (as timeit does)
+    gc.collect()
+    gc.disable()
     # five consecutive windows of the timed steps (each step of the full loop
     # ends in a synchronising force read, so the marks need no extra sync)
     nwin = 5 if full_loop and steps >= 50 else 1
@@ -113,6 +117,7 @@ def run_case(psm, torch, spec, storage, steps, warmup, autotune, launch=None, fu
     eng.synchronize()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    gc.enable()
     marks.append(t1)
     n_launch, kern_ms = eng.get_timing()
     eng.set_timing(False)
@@ -364,11 +369,14 @@ def run_dense_moving(psm, torch, inputs, n=768, steps=500, warmup=5, device=Fals
         eng.synchronize()
         eng.reset_timing()
         eng.set_timing(True)
+        gc.collect()
+        gc.disable()
         t0 = time.perf_counter()
         for _ in range(steps):
             one(record=True)
         eng.get_forces(0)
         dt = time.perf_counter() - t0
+        gc.enable()
         nl, kms = eng.get_timing()
         eng.set_timing(False)
         launches = sum(a.elapsed_time(b) for a, b, _ in evs) / steps

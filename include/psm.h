@@ -290,10 +290,13 @@ int psm_clear_tune_cache(void);
 /* Enable (1) / disable (0) HIP-graph replay of 10-step sequences in psm_step. */
 int psm_set_graph(psm_ctx* ctx, int enable);
 
-/* Kernel timing: when enabled, psm_step records HIP events on the context's
- * stream around every launch of the step kernel (eager launches only).
+/* Kernel timing: when enabled, psm_step launches every step eagerly (no graph
+ * replay) and records HIP events on the context's stream around every launch
+ * of the step kernel.
  * psm_get_timing synchronises and returns the number of timed launches and
- * their summed duration in ms; psm_reset_timing clears both. */
+ * their summed duration in ms; psm_reset_timing clears both. The events come
+ * from a pool of 128 pairs created by psm_set_timing(ctx, 1); every 128th
+ * timed launch first waits for the earlier ones to finish and adds them up. */
 int psm_set_timing(psm_ctx* ctx, int enable);
 int psm_get_timing(psm_ctx* ctx, long long* launches, double* total_ms);
 int psm_reset_timing(psm_ctx* ctx);

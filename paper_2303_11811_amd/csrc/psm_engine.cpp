@@ -852,12 +852,41 @@ static ReduceParams reduce_params(psm_ctx* c) {
     return rp;
 }
 
-static hipEvent_t next_event(psm_ctx* c) {
-    if (c->ev_used == c->ev.size()) {
+// Kernel timing keeps a fixed pool of events (created when timing is turned
+// on, so that none is created inside a timed loop). When the pool is full,
+// the recorded pairs are folded into the totals: the last recorded event is
+// waited for (every earlier one is then complete) and the pool starts over.
+constexpr size_t kEvPool = 256;
+
+static int create_events(psm_ctx* c) {
+    if (c->ev.size() >= kEvPool) return PSM_OK;
+    while (c->ev.size() < kEvPool) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        HIP_TRY(hipEventCreate(&e));
         c->ev.push_back(e);
     }
+    // record each event once here: a first record costs more than later ones,
+    // and the first timed steps should not pay for it
+    for (hipEvent_t e : c->ev) HIP_TRY(hipEventRecord(e, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return PSM_OK;
+}
+
+static int fold_events(psm_ctx* c) {
+    if (c->ev_used >= 2) HIP_TRY(hipEventSynchronize(c->ev[c->ev_used - 1]));
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+        c->timed_ms += ms;
+        c->timed_launches++;
+    }
+    c->ev_used = 0;
+    return PSM_OK;
+}
+
+static hipEvent_t next_event(psm_ctx* c) {
+    if (c->ev_used == kEvPool && fold_events(c) != PSM_OK) return nullptr;
+    if (c->ev_used == c->ev.size() && create_events(c) != PSM_OK) return nullptr;
     return c->ev[c->ev_used++];
 }
 
@@ -867,14 +896,15 @@ static int enqueue_step(psm_ctx* c, bool timed) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
         e0 = next_event(c);
-        e1 = next_event(c);
-        if (e0) HIP_TRY(hipEventRecord(e0, c->stream));
+        e1 = e0 ? next_event(c) : nullptr;
+        if (!e0 || !e1) return fail(PSM_EHIP, "timing events: %s", g_err.c_str());
+        HIP_TRY(hipEventRecord(e0, c->stream));
     }
     // the persistent grid's tile counters start at zero (a kernel, not a
     // memset: the step may be captured into a graph)
     if (kp.queue) HIP_TRY(launch_fill_int(kp.queue, NXCD, 0, c->stream));
     HIP_TRY(launch_step(c->storage, c->map_mode, c->ts.filter != 0, kp, c->grid, c->stream));
-    if (timed && e1) HIP_TRY(hipEventRecord(e1, c->stream));
+    if (timed) HIP_TRY(hipEventRecord(e1, c->stream));
     HIP_TRY(launch_reduce(reduce_params(c), c->stream));
     c->parity ^= 1;
     return PSM_OK;
@@ -1179,6 +1209,10 @@ extern "C" int psm_set_graph(psm_ctx* c, int enable) {
 
 extern "C" int psm_set_timing(psm_ctx* c, int enable) {
     if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    if (enable) {
+        int rc = create_events(c);
+        if (rc) return rc;
+    }
     c->timing = enable != 0;
     return PSM_OK;
 }
@@ -1186,13 +1220,8 @@ extern "C" int psm_set_timing(psm_ctx* c, int enable) {
 extern "C" int psm_get_timing(psm_ctx* c, long long* launches, double* total_ms) {
     if (!c) return fail(PSM_EINVAL, "ctx is NULL");
     HIP_TRY(hipStreamSynchronize(c->stream));
-    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
-        float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
-        c->timed_ms += ms;
-        c->timed_launches++;
-    }
-    c->ev_used = 0;
+    int rc = fold_events(c);
+    if (rc) return rc;
     if (launches) *launches = c->timed_launches;
     if (total_ms) *total_ms = c->timed_ms;
     return PSM_OK;

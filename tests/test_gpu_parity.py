@@ -286,6 +286,30 @@ def test_persistent_grid_matches_one_workgroup_per_tile(storage):
             assert all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
+def test_kernel_timing_counts_every_eager_launch():
+    """Timing events come from a fixed pool that is folded into the totals
+    when full: 300 steps (more than the pool's 128 pairs) count 300 launches
+    with a positive total; with timing on, steps run eagerly even where graphs
+    are enabled, so they are counted too; reset clears."""
+    spec = inputs.random_small((40, 36, 28), 3, (3.0, 4.0), seed=95, tau=0.7)
+    eng = make_engine([spec])
+    eng.set_pdfs(0, initial_f(spec))
+    eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+    eng.set_timing(True)
+    eng.step(300)
+    n, ms = eng.get_timing()
+    assert n == 300 and ms > 0.0
+    eng.set_graph(True)
+    eng.step(20)
+    assert eng.get_timing()[0] == 320
+    eng.set_graph(False)
+    eng.reset_timing()
+    eng.step(5)
+    n, ms5 = eng.get_timing()
+    assert n == 5 and 0.0 < ms5 < ms
+    eng.close()
+
+
 @pytest.mark.parametrize("storage", [psm.PSM_FP64, psm.PSM_FP16DEV])
 def test_pattern_copy_leaves_the_state(storage):
     """The access-pattern bandwidth reference writes only the grid the next

@@ -314,17 +314,21 @@ __device__ __forceinline__ float wrap32(float t, float L, float invL) { return f
 #define PSM_WAVES_PER_EU_DEV 4
 #endif
 // Pull order of the step kernel (measured per storage form): the FP32 form
-// pulls the next cell's values while it works on the current one; FP64 and
-// FP16 pull each cell's values after its mapping (pulling earlier, or ahead,
-// cost FP64 registers spilled to scratch and did not speed up FP16).
+// pulls the next cell's values while it works on the current one; FP64 issues
+// each cell's pulls before its mapping (not with the candidate filter, whose
+// registers that would spill); FP16 pulls after the mapping (earlier or ahead
+// was slower there).
 #ifndef PSM_PREFETCH_F32
 #define PSM_PREFETCH_F32 1
 #endif
 #ifndef PSM_PREFETCH_F16
 #define PSM_PREFETCH_F16 0
 #endif
-#ifndef PSM_EARLY_PULLS
-#define PSM_EARLY_PULLS 0
+#ifndef PSM_EARLY_PULLS_F64
+#define PSM_EARLY_PULLS_F64 1
+#endif
+#ifndef PSM_EARLY_PULLS_F16
+#define PSM_EARLY_PULLS_F16 0
 #endif
 
 // pull of the 19 values of one cell from the source planes z (rz), z-1 (rm)
@@ -524,7 +528,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S::DEV ? PSM
         // z) while the current one is mapped and collided; EARLY issues the
         // current cell's pulls before its mapping.
         constexpr bool PREF = S::DEV && !FILT && (S::SCALED ? PSM_PREFETCH_F16 : PSM_PREFETCH_F32);
-        constexpr bool EARLY = !PREF && PSM_EARLY_PULLS;
+        constexpr bool EARLY = !PREF && !FILT && (S::DEV ? (S::SCALED && PSM_EARLY_PULLS_F16) : PSM_EARLY_PULLS_F64);
         R fn[NQ];
         if constexpr (PREF) {
             const int z0 = tcz * TZ;

@@ -295,8 +295,9 @@ int psm_set_graph(psm_ctx* ctx, int enable);
  * of the step kernel.
  * psm_get_timing synchronises and returns the number of timed launches and
  * their summed duration in ms; psm_reset_timing clears both. The events come
- * from a pool of 128 pairs created by psm_set_timing(ctx, 1); every 128th
- * timed launch first waits for the earlier ones to finish and adds them up. */
+ * from a pool of 128 pairs that the first psm_set_timing(ctx, 1) creates and
+ * records once (it synchronises the stream then); every 128th timed launch
+ * first waits for the earlier ones to finish and adds them up. */
 int psm_set_timing(psm_ctx* ctx, int enable);
 int psm_get_timing(psm_ctx* ctx, long long* launches, double* total_ms);
 int psm_reset_timing(psm_ctx* ctx);

@@ -66,17 +66,24 @@ static int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 // Largest number of tiles the bounding box [x-(r+1), x+(r+1)] can touch along
 // an axis of L cells cut into tiles of T cells.
+// Most tiles of one axis that a sphere's cell range can touch. The range
+// spans at most E = floor(2(r+1)) + 2 cells. On a periodic axis whose last
+// tile is short (r_last = L - (nt-1)T cells), a range that wraps through it
+// touches 1 + ceil((a - r_last)/T) tiles before the wrap and ceil((E - a)/T)
+// after it (a cells before the wrap), at most 2 + ceil((E - r_last)/T) in
+// all; without a wrap it touches at most 1 + ceil((E-1)/T), which is no more.
 static int max_tiles_axis(double rmax, int T, int L) {
     int E = (int)std::floor(2.0 * (rmax + 1.0)) + 2;
     int nt = cdiv(L, T);
-    return std::min(nt, cdiv(E, T) + 1);
+    int r_last = L - (nt - 1) * T;
+    return std::min(nt, 2 + cdiv(std::max(E - r_last, 0), T));
 }
 
 // ---------------------------------------------------------------------------
 // Workspace layout
 
 struct Layout {
-    size_t off_boxes, off_tbase, off_partbox, off_pt, off_acc, off_fprev, off_prevok, off_tcnt, off_toff, off_tpid,
+    size_t off_boxes, off_tbase, off_partbox, off_pt, off_acc, off_fprev, off_prevok, off_tcnt, off_toff, off_tpid, off_tslot,
         off_partial, off_misc, off_statpart, off_scan, total;
     std::vector<size_t> off_grid[2];
     std::vector<int> pblk;
@@ -174,6 +181,7 @@ static Layout make_layout(const psm_box_desc* boxes, int nbox, int storage) {
     L.off_tcnt = take(sizeof(int) * (size_t)Tmax);
     L.off_toff = take(sizeof(int) * ((size_t)Tmax + 1));
     L.off_tpid = take(sizeof(int) * (size_t)L.cap_max);
+    L.off_tslot = take(sizeof(int) * (size_t)L.cap_max);
     L.off_partial = take(sizeof(double) * 6 * (size_t)L.cap_max);
     L.off_misc = take(256);
     L.off_statpart = take(sizeof(double) * 4 * (size_t)stats_blocks() + 64);
@@ -217,7 +225,7 @@ struct psm_ctx {
     int* d_tbase = nullptr;
     int* d_partbox = nullptr;
     Particles P{};
-    int *d_tcnt = nullptr, *d_toff = nullptr, *d_tpid = nullptr;
+    int *d_tcnt = nullptr, *d_toff = nullptr, *d_tpid = nullptr, *d_tslot = nullptr;
     double* d_partial = nullptr;
     int* d_misc = nullptr;               // [0..1] bin stats, [8..9] dropped (u64), [16] device error word,
                                          // [32..39] tile counters of the persistent grid
@@ -288,6 +296,17 @@ static void assign_tiles(psm_ctx* c) {
         base += bx.ntx * bx.nty * bx.ntz;
     }
     c->T_total = base;
+    // force-partial slots: per sphere, one per tile its bounding box can
+    // touch at this tile shape (at most the capacity the layout reserves)
+    long long pbase = 0;
+    for (int b = 0; b < c->nbox; ++b) {
+        const psm_box_desc& d = c->desc[b];
+        BoxDev& bx = c->box[b];
+        bx.pstride = max_tiles_axis(d.max_radius, c->ts.tx, d.nx) * max_tiles_axis(d.max_radius, c->ts.ty, d.ny) *
+                     max_tiles_axis(d.max_radius, c->ts.tz, d.nz);
+        bx.pbase = (int)pbase;
+        pbase += (long long)d.max_particles * bx.pstride;
+    }
     int dev = 0, ncu = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -309,6 +328,8 @@ static int rebuild_lists(psm_ctx* c) {
     bp.tile_cnt = c->d_tcnt;
     bp.tile_off = c->d_toff;
     bp.tile_pid = c->d_tpid;
+    bp.tile_slot = c->d_tslot;
+    bp.partial = c->d_partial;
     bp.P_total = c->P_total;
     bp.T_total = c->T_total;
     bp.ts = c->ts;
@@ -340,6 +361,8 @@ static int rebuild_lists_async(psm_ctx* c) {
     bp.tile_cnt = c->d_tcnt;
     bp.tile_off = c->d_toff;
     bp.tile_pid = c->d_tpid;
+    bp.tile_slot = c->d_tslot;
+    bp.partial = c->d_partial;
     bp.P_total = c->P_total;
     bp.T_total = c->T_total;
     bp.ts = c->ts;
@@ -389,7 +412,10 @@ extern "C" int psm_workspace_size(const psm_box_desc* boxes, int nbox, int stora
     if (!bytes) return fail(PSM_EINVAL, "bytes is NULL");
     int rc = validate(boxes, nbox, storage);
     if (rc) return rc;
-    *bytes = make_layout(boxes, nbox, storage).total;
+    Layout L = make_layout(boxes, nbox, storage);
+    if (L.cap_max >= (1LL << 31))
+        return fail(PSM_EINVAL, "tile lists would need %lld entries (at most 2^31 - 1)", L.cap_max);
+    *bytes = L.total;
     return PSM_OK;
 }
 
@@ -402,6 +428,8 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
     if (!dev_workspace) return fail(PSM_EINVAL, "workspace is NULL");
     if (((uintptr_t)dev_workspace) & 255) return fail(PSM_EINVAL, "workspace must be 256-byte aligned");
     Layout L = make_layout(boxes, nbox, storage);
+    if (L.cap_max >= (1LL << 31))
+        return fail(PSM_EINVAL, "tile lists would need %lld entries (at most 2^31 - 1)", L.cap_max);
     if (workspace_bytes < L.total)
         return fail(PSM_EINVAL, "workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
     if (storage == PSM_FP16DEV) {
@@ -525,6 +553,7 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
     c->d_tcnt = (int*)(c->ws + L.off_tcnt);
     c->d_toff = (int*)(c->ws + L.off_toff);
     c->d_tpid = (int*)(c->ws + L.off_tpid);
+    c->d_tslot = (int*)(c->ws + L.off_tslot);
     c->d_partial = (double*)(c->ws + L.off_partial);
     c->d_misc = (int*)(c->ws + L.off_misc);
     c->d_flags = c->d_misc + 16;
@@ -827,6 +856,7 @@ static int step_params(psm_ctx* c, int parity, StepParams& kp) {
     kp.P = c->P;
     kp.tile_off = c->d_toff;
     kp.tile_pid = c->d_tpid;
+    kp.tile_slot = c->d_tslot;
     kp.partial = c->d_partial;
     kp.T_total = c->T_total;
     kp.tx = c->ts.tx; kp.ty = c->ts.ty; kp.tz = c->ts.tz;

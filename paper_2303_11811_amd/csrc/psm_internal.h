@@ -31,6 +31,10 @@ struct BoxDev {
     int nx, ny, nz, N;
     int ntx, nty, ntz, tile_base;   // tiles per axis, first global tile
     int part_base, np, mapping, nsub;
+    // force partials of a sphere: slots pbase + (local id) * pstride + k for
+    // the k-th tile of its bounding box (pstride bounds the tiles a sphere of
+    // this box can touch at the current tile shape)
+    int pstride, pbase;
     // PDF storage: each z-plane holds pblk blocks of 64 cells (pitch*ny
     // rounded up); a block stores its 19 directions one after another, 64
     // values each. Cell (x, y) of a plane is in-plane cell x + pitch*y.
@@ -258,7 +262,8 @@ struct StepParams {
     Particles P;
     const int* tile_off;        // [T+1]
     const int* tile_pid;        // [entries] global particle ids
-    double* partial;            // [entries][6]
+    const int* tile_slot;       // [entries] force-partial slot of each entry
+    double* partial;            // [slots][6]
     int T_total;
     int tx, ty, tz;
     int parity;
@@ -286,6 +291,8 @@ struct BinParams {
     int* tile_cnt;
     int* tile_off;
     int* tile_pid;
+    int* tile_slot;             // [entries] force-partial slot of each entry
+    double* partial;            // [slots][6], zeroed for an entry a full list drops
     int P_total;
     int T_total;
     TileShape ts;

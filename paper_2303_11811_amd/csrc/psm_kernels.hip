@@ -369,7 +369,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S::DEV ? PSM
     // deviation forms) the velocities
     __shared__ float s_qx[MAXC], s_qy[MAXC], s_qz[MAXC], s_lim2[MAXC], s_rf[MAXC], s_frf[MAXC];
     __shared__ float s_uf[6][MAXC];
-    __shared__ int s_pid[MAXC];
+    __shared__ int s_pid[MAXC], s_slot[MAXC];
     __shared__ double s_acc[NWAVE][6][MAXC];
     __shared__ unsigned long long s_cmask[NWAVE][TZ_MAX];
 
@@ -435,6 +435,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S::DEV ? PSM
             for (int c = tid; c < nc; c += WG) {
                 int p = kp.tile_pid[e0 + c];
                 s_pid[c] = p;
+                s_slot[c] = kp.tile_slot[e0 + c];
                 const double px = kp.P.x[p], py = kp.P.y[p], pz = kp.P.z[p], pr = kp.P.r[p], pfr = kp.P.fr[p];
                 s_px[c] = px; s_py[c] = py; s_pz[c] = pz;
                 s_pr[c] = pr; s_pfr[c] = pfr;
@@ -859,7 +860,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(S::DEV ? PSM
                 double s = 0.0;
 #pragma unroll
                 for (int w = 0; w < NWAVE; ++w) s += s_acc[w][k6][c];
-                kp.partial[(long long)(e0 + c) * 6 + k6] = s;
+                kp.partial[(long long)s_slot[c] * 6 + k6] = s;
             }
         }
         __syncthreads();
@@ -894,17 +895,12 @@ __global__ __launch_bounds__(256) void k_reduce_forces(ReduceParams rp) {
         AxisTiles ay = axis_tiles(lo, hi, bx.ny, rp.ts.ty, bx.nty);
         aabb_cells(rp.P.z[p], rp.P.r[p], lo, hi);
         AxisTiles az = axis_tiles(lo, hi, bx.nz, rp.ts.tz, bx.ntz);
-        const int nxt = ax.count(), nyt = ay.count(), nzt = az.count();
-        const int ntot = nxt * nyt * nzt;
+        const int ntot = ax.count() * ay.count() * az.count();
+        // the sphere's slots: one per tile of its bounding box, in that order
+        const double* pp = rp.partial + ((long long)bx.pbase + (long long)(p - bx.part_base) * bx.pstride) * 6;
         for (int k = lane; k < ntot; k += 64) {
-            int kx = k % nxt, ky = (k / nxt) % nyt, kz = k / (nxt * nyt);
-            int t = bx.tile_base + ax.at(kx) + bx.ntx * (ay.at(ky) + bx.nty * az.at(kz));
-            int e0 = rp.tile_off[t], e1 = rp.tile_off[t + 1];
-            for (int e = e0; e < e1; ++e)
-                if (rp.tile_pid[e] == p) {
-                    for (int c = 0; c < 6; ++c) acc[c] += rp.partial[(long long)e * 6 + c];
-                    break;
-                }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) acc[c] += pp[(long long)k * 6 + c];
         }
     }
 #pragma unroll
@@ -945,7 +941,14 @@ __global__ __launch_bounds__(256) void k_bin(BinParams bp) {
             // is flagged from the uncapped maximum)
             int pos = atomicSub(&bp.tile_cnt[t], 1) - 1;
             long long e = (long long)bp.tile_off[t] + pos;
-            if (pos < MAXC && e < bp.cap) bp.tile_pid[e] = p;
+            const long long slot = (long long)bx.pbase + (long long)(p - bx.part_base) * bx.pstride + k;
+            if (pos < MAXC && e < bp.cap) {
+                bp.tile_pid[e] = p;
+                bp.tile_slot[e] = (int)slot;
+            } else {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) bp.partial[slot * 6 + c] = 0.0;
+            }
         }
     }
 }

@@ -172,8 +172,23 @@ int psm_step(psm_ctx* ctx, int nsteps);
 /* Hydrodynamic force and torque of eqs. (21)-(22) on every sphere of box
  * `box` from the last executed step. F, T: host (n,3) FP64 (n = particles set).
  * Synchronises and reports the device error word (see the conventions). Before
- * any step: zeros. */
+ * any step: zeros. With the force read-back on (psm_set_force_readback) and
+ * no step enqueued since the last psm_step, it waits only for the copy that
+ * psm_step made, not for work enqueued after it. */
 int psm_get_forces(psm_ctx* ctx, int box, double* F, double* T);
+
+/* Force read-back for a host that integrates the spheres (the per-step
+ * force transfer to the host of Sec. 3.2). enable != 0: every psm_step ends
+ * by copying the force and torque sums of all boxes and the device error word
+ * into pinned host memory (one copy of 48 B per sphere slot); psm_get_forces
+ * then waits for that copy only, so that a position upload and its re-binning
+ * enqueued after the step run while the host reads the forces and updates
+ * the velocities. The error word is the one the copy saw: an overflow raised
+ * by such a re-binning is reported by the psm_get_forces after the next step
+ * (that step runs on the cut lists and stays in bounds). An error bit in the
+ * copy makes psm_get_forces synchronise as without the read-back. Off by
+ * default; enable = 0 turns it off. PSM_EINVAL for a NULL ctx. */
+int psm_set_force_readback(psm_ctx* ctx, int enable);
 
 /* Solid fractions of the current particles (the mapping of the step, in FP64;
  * the FP16-deviation step evaluates the linear approximation in FP32, within

@@ -66,6 +66,7 @@ _SIGS = {
     "psm_get_stats": ([_P, ctypes.c_int, _D, _D, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
     "psm_set_drift_check": ([_P, ctypes.c_int, ctypes.c_double], ctypes.c_int),
     "psm_set_strict_slots": ([_P, ctypes.c_int], ctypes.c_int),
+    "psm_set_force_readback": ([_P, ctypes.c_int], ctypes.c_int),
     "psm_set_launch": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "psm_get_launch": ([_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
@@ -262,6 +263,10 @@ def psm_set_strict_slots(ctx, enable):
     return _check(lib().psm_set_strict_slots(ctx, int(bool(enable))))
 
 
+def psm_set_force_readback(ctx, enable):
+    return _check(lib().psm_set_force_readback(ctx, int(bool(enable))))
+
+
 def psm_set_launch(ctx, tx, ty, tz, flags=0):
     return _check(lib().psm_set_launch(ctx, int(tx), int(ty), int(tz), int(flags)))
 
@@ -455,6 +460,9 @@ class Engine:
 
     def set_strict_slots(self, enable):
         psm_set_strict_slots(self.ctx, enable)
+
+    def set_force_readback(self, enable):
+        psm_set_force_readback(self.ctx, enable)
 
     def set_launch(self, tx, ty, tz, flags=0):
         psm_set_launch(self.ctx, tx, ty, tz, flags)

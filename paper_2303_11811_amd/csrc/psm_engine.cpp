@@ -175,7 +175,7 @@ static Layout make_layout(const psm_box_desc* boxes, int nbox, int storage) {
     L.off_tbase = take(sizeof(int) * (nbox + 1));
     L.off_partbox = take(sizeof(int) * std::max(P, 1));
     L.off_pt = take(sizeof(double) * 11 * std::max(P, 1));
-    L.off_acc = take(sizeof(double) * 6 * std::max(P, 1));
+    L.off_acc = take(sizeof(double) * 6 * std::max(P, 1) + 64);   // + the device error word
     L.off_fprev = take(sizeof(double) * 6 * std::max(P, 1));
     L.off_prevok = take(sizeof(int) * std::max(P, 1));
     L.off_tcnt = take(sizeof(int) * (size_t)Tmax);
@@ -227,9 +227,9 @@ struct psm_ctx {
     Particles P{};
     int *d_tcnt = nullptr, *d_toff = nullptr, *d_tpid = nullptr, *d_tslot = nullptr;
     double* d_partial = nullptr;
-    int* d_misc = nullptr;               // [0..1] bin stats, [8..9] dropped (u64), [16] device error word,
+    int* d_misc = nullptr;               // [0..1] bin stats, [8..9] dropped (u64),
                                          // [32..39] tile counters of the persistent grid
-    int* d_flags = nullptr;              // d_misc + 16 (FLAG_* bits)
+    int* d_flags = nullptr;              // device error word (FLAG_* bits), right after the force sums
     int* h_flags = nullptr;              // pinned copy of the device error word
     double* d_statpart = nullptr;
     int* d_scan = nullptr;               // scan scratch (chunk sums and maxima)
@@ -241,6 +241,11 @@ struct psm_ctx {
     size_t h_stage_n = 0;
     size_t h_half = 0;               // doubles per upload half
     double* h_read = nullptr;        // read-back area (forces, stats)
+    // force read-back at the end of psm_step (psm_set_force_readback): the
+    // force sums of all boxes and the error word, copied in one piece
+    bool rb_on = false, rb_valid = false;
+    double* h_rb = nullptr;          // [6 P_total] sums, then the error word
+    hipEvent_t rb_ev = nullptr;
     hipEvent_t stage_ev[2] = {nullptr, nullptr};
     int stage_next = 0;
     std::vector<std::vector<double>> last_r, last_fr;   // f(r) cache per box
@@ -556,7 +561,7 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
     c->d_tslot = (int*)(c->ws + L.off_tslot);
     c->d_partial = (double*)(c->ws + L.off_partial);
     c->d_misc = (int*)(c->ws + L.off_misc);
-    c->d_flags = c->d_misc + 16;
+    c->d_flags = (int*)(c->P.acc + 6 * P1);
     c->d_statpart = (double*)(c->ws + L.off_statpart);
     c->d_scan = (int*)(c->ws + L.off_scan);
     c->last_xr.assign(nbox, std::vector<double>());
@@ -566,12 +571,13 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
         if (e != hipSuccess && err == PSM_OK) err = fail(PSM_EHIP, "%s: %s", what, hipGetErrorString(e));
     };
     c->h_half = 11 * P1 + 64;
-    c->h_stage_n = 2 * c->h_half + 9 * P1 + 64;
+    c->h_stage_n = 2 * c->h_half + 9 * P1 + 64 + 6 * P1 + 64;
     hip_ok(hipHostMalloc((void**)&c->h_stage, sizeof(double) * c->h_stage_n, hipHostMallocDefault), "hipHostMalloc");
     if (err) { delete c; return err; }
     c->h_read = c->h_stage + 2 * c->h_half;
     c->h_flags = (int*)(c->h_read + 9 * P1);   // inside the read area's padding
     *c->h_flags = 0;
+    c->h_rb = c->h_read + 9 * P1 + 64;
     {
         const char* e = std::getenv("PSM_STRICT_SLOTS");
         c->strict_slots = e && std::strcmp(e, "1") == 0;
@@ -579,6 +585,7 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
     c->drift_tol.assign(nbox, 0.0);
     c->ref_mass.assign(nbox, std::nan(""));
     for (int h = 0; h < 2; ++h) hip_ok(hipEventCreateWithFlags(&c->stage_ev[h], hipEventDisableTiming), "event");
+    hip_ok(hipEventCreateWithFlags(&c->rb_ev, hipEventDisableTiming), "event");
     if (err) { (void)hipHostFree(c->h_stage); delete c; return err; }
     c->last_r.assign(nbox, std::vector<double>());
     c->last_fr.assign(nbox, std::vector<double>());
@@ -588,7 +595,7 @@ extern "C" int psm_create(const psm_box_desc* boxes, int nbox, int storage, doub
         for (int p = 0; p < boxes[b].max_particles; ++p) partbox[c->box[b].part_base + p] = b;
     hip_ok(hipMemcpyAsync(c->d_partbox, partbox.data(), sizeof(int) * P1, hipMemcpyHostToDevice, c->stream),
            "upload part_box");
-    hip_ok(hipMemsetAsync(c->P.acc, 0, sizeof(double) * 6 * P1, c->stream), "clear forces");
+    hip_ok(hipMemsetAsync(c->P.acc, 0, sizeof(double) * 6 * P1 + 64, c->stream), "clear forces and error word");
     hip_ok(hipMemsetAsync(pt, 0, sizeof(double) * 11 * P1, c->stream), "clear particles");
     hip_ok(hipMemsetAsync(c->P.fprev, 0, sizeof(double) * 6 * P1, c->stream), "clear previous forces");
     hip_ok(hipMemsetAsync(c->P.prev_ok, 0, sizeof(int) * P1, c->stream), "clear previous-force flags");
@@ -615,6 +622,7 @@ extern "C" int psm_destroy(psm_ctx* c) {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     for (int h = 0; h < 2; ++h)
         if (c->stage_ev[h]) (void)hipEventDestroy(c->stage_ev[h]);
+    if (c->rb_ev) (void)hipEventDestroy(c->rb_ev);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     delete c;
     return PSM_OK;
@@ -772,8 +780,10 @@ extern "C" int psm_set_particles(psm_ctx* c, int box, int n, const double* x, co
 
 // Upload some columns of the sphere table of box `box` (n spheres, the
 // current count) through the pinned staging: cols[k] (host, row-major (n,3))
-// goes to the three device columns first_col[k] .. first_col[k] + 2. Wraps
-// positions (first column 0) into the box. Asynchronous.
+// goes to the three device columns first_col[k] .. first_col[k] + 2. Checks
+// each value while it stages it (finite; a position column also keeps r + 1
+// from the walls and is wrapped into the box) and enqueues nothing when one
+// fails. Asynchronous.
 static int upload_columns(psm_ctx* c, int box, int n, const double* const* cols, const int* first_col, int ncols) {
     const psm_box_desc& d = c->desc[box];
     const int m = d.max_particles;
@@ -782,6 +792,8 @@ static int upload_columns(psm_ctx* c, int box, int n, const double* const* cols,
     HIP_TRY(hipEventSynchronize(c->stage_ev[h]));
     double* st = c->h_stage + (size_t)h * c->h_half;
     const double L[3] = {(double)d.nx, (double)d.ny, (double)d.nz};
+    const int walled[3] = {d.walls_x, d.walls_y, d.walls_z};
+    const std::vector<double>& r = c->last_r[box];
     const int pb = c->box[box].part_base;
     const size_t P1 = (size_t)std::max(c->P_total, 1);
     double* dev_cols[11] = {c->P.x, c->P.y, c->P.z, c->P.r, c->P.fr, c->P.ux, c->P.uy, c->P.uz, c->P.ox, c->P.oy, c->P.oz};
@@ -790,16 +802,28 @@ static int upload_columns(psm_ctx* c, int box, int n, const double* const* cols,
         const double* v = cols[k];
         if (first_col[k] == 0) {
             for (int p = 0; p < n; ++p)
-                for (int a = 0; a < 3; ++a) sk[(size_t)a * m + p] = wrap_coord(v[3 * p + a], L[a]);
-        } else {
+                for (int a = 0; a < 3; ++a) {
+                    const double xa = v[3 * p + a];
+                    if (!std::isfinite(xa)) return fail(PSM_EINVAL, "particle %d: non-finite position", p);
+                    if (walled[a] && !(xa >= r[p] + 1.0 && xa <= L[a] - r[p] - 1.0))
+                        return fail(PSM_EINVAL, "particle %d: centre closer than r + 1 to a wall", p);
+                    sk[(size_t)a * m + p] = wrap_coord(xa, L[a]);
+                }
+        } else if (v) {
             for (int p = 0; p < n; ++p)
-                for (int a = 0; a < 3; ++a) sk[(size_t)a * m + p] = v ? v[3 * p + a] : 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double va = v[3 * p + a];
+                    if (!std::isfinite(va)) return fail(PSM_EINVAL, "particle %d: non-finite velocity", p);
+                    sk[(size_t)a * m + p] = va;
+                }
+        } else {
+            for (int a = 0; a < 3; ++a) std::fill(sk + (size_t)a * m, sk + (size_t)a * m + n, 0.0);
         }
-        // the three device columns are P_total apart: one strided copy
-        if (n > 0)
-            HIP_TRY(hipMemcpy2DAsync(dev_cols[first_col[k]] + pb, sizeof(double) * P1, sk, sizeof(double) * m,
-                                     sizeof(double) * n, 3, hipMemcpyHostToDevice, c->stream));
     }
+    // the three device columns of each are P_total apart: one strided copy
+    for (int k = 0; k < ncols && n > 0; ++k)
+        HIP_TRY(hipMemcpy2DAsync(dev_cols[first_col[k]] + pb, sizeof(double) * P1, st + (size_t)3 * k * m,
+                                 sizeof(double) * m, sizeof(double) * n, 3, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipEventRecord(c->stage_ev[h], c->stream));
     return PSM_OK;
 }
@@ -816,16 +840,6 @@ extern "C" int psm_set_particle_positions(psm_ctx* c, int box, int n, const doub
     int rc = check_update_args(c, box, n);
     if (rc) return rc;
     if (n > 0 && !x) return fail(PSM_EINVAL, "x is NULL");
-    const psm_box_desc& d = c->desc[box];
-    const int walled[3] = {d.walls_x, d.walls_y, d.walls_z};
-    const int dims3[3] = {d.nx, d.ny, d.nz};
-    const std::vector<double>& r = c->last_r[box];
-    for (int p = 0; p < n; ++p)
-        for (int a = 0; a < 3; ++a) {
-            if (!std::isfinite(x[3 * p + a])) return fail(PSM_EINVAL, "particle %d: non-finite position", p);
-            if (walled[a] && !(x[3 * p + a] >= r[p] + 1.0 && x[3 * p + a] <= dims3[a] - r[p] - 1.0))
-                return fail(PSM_EINVAL, "particle %d: centre closer than r + 1 to a wall", p);
-        }
     const double* cols[1] = {x};
     const int first[1] = {0};
     if ((rc = upload_columns(c, box, n, cols, first, 1))) return rc;
@@ -837,10 +851,6 @@ extern "C" int psm_set_particle_velocities(psm_ctx* c, int box, int n, const dou
     int rc = check_update_args(c, box, n);
     if (rc) return rc;
     if (n > 0 && !U) return fail(PSM_EINVAL, "U is NULL");
-    for (int p = 0; p < n; ++p)
-        for (int a = 0; a < 3; ++a)
-            if (!std::isfinite(U[3 * p + a]) || (omega && !std::isfinite(omega[3 * p + a])))
-                return fail(PSM_EINVAL, "particle %d: non-finite velocity", p);
     const double* cols[2] = {U, omega};
     const int first[2] = {5, 8};
     if ((rc = upload_columns(c, box, n, cols, first, 2))) return rc;
@@ -937,6 +947,7 @@ static int enqueue_step(psm_ctx* c, bool timed) {
     if (timed) HIP_TRY(hipEventRecord(e1, c->stream));
     HIP_TRY(launch_reduce(reduce_params(c), c->stream));
     c->parity ^= 1;
+    c->rb_valid = false;
     return PSM_OK;
 }
 
@@ -980,6 +991,21 @@ extern "C" int psm_step(psm_ctx* c, int nsteps) {
         int rc = enqueue_step(c, c->timing);
         if (rc) return rc;
     }
+    if (c->rb_on && nsteps > 0) {
+        // the force sums of every box and the error word, one contiguous copy
+        const size_t P1 = (size_t)std::max(c->P_total, 1);
+        HIP_TRY(hipMemcpyAsync(c->h_rb, c->P.acc, sizeof(double) * 6 * P1 + sizeof(int), hipMemcpyDeviceToHost,
+                               c->stream));
+        HIP_TRY(hipEventRecord(c->rb_ev, c->stream));
+        c->rb_valid = true;
+    }
+    return PSM_OK;
+}
+
+extern "C" int psm_set_force_readback(psm_ctx* c, int enable) {
+    if (!c) return fail(PSM_EINVAL, "ctx is NULL");
+    c->rb_on = enable != 0;
+    c->rb_valid = false;
     return PSM_OK;
 }
 
@@ -989,10 +1015,21 @@ extern "C" int psm_get_forces(psm_ctx* c, int box, double* F, double* T) {
     int n = c->np[box];
     if (n == 0) return (rc = sync_with_flags(c)) ? rc : take_flags(c);
     if (!F || !T) return fail(PSM_EINVAL, "F/T is NULL");
-    double* st = c->h_read;
-    HIP_TRY(hipMemcpyAsync(st, c->P.acc + 6LL * c->box[box].part_base, sizeof(double) * 6 * n,
-                           hipMemcpyDeviceToHost, c->stream));
-    if ((rc = sync_with_flags(c)) || (rc = take_flags(c))) return rc;
+    const double* st;
+    if (c->rb_valid) {
+        // the copy psm_step made: wait for it, not for work enqueued after it
+        HIP_TRY(hipEventSynchronize(c->rb_ev));
+        int f = *(const int*)(c->h_rb + 6 * (size_t)std::max(c->P_total, 1));
+        if (!c->strict_slots) f &= ~FLAG_SLOT_OVERFLOW;
+        // an error bit: report it the usual way, from the end of the stream
+        if (f && ((rc = sync_with_flags(c)) || (rc = take_flags(c)))) return rc;
+        st = c->h_rb + 6LL * c->box[box].part_base;
+    } else {
+        HIP_TRY(hipMemcpyAsync(c->h_read, c->P.acc + 6LL * c->box[box].part_base, sizeof(double) * 6 * n,
+                               hipMemcpyDeviceToHost, c->stream));
+        if ((rc = sync_with_flags(c)) || (rc = take_flags(c))) return rc;
+        st = c->h_read;
+    }
     for (int p = 0; p < n; ++p)
         for (int a = 0; a < 3; ++a) {
             F[3 * p + a] = st[6 * p + a];

@@ -85,6 +85,7 @@ def test_null_context_calls():
     assert L.psm_set_launch(None, 64, 4, 1, 0) == psm.PSM_EINVAL
     assert L.psm_set_drift_check(None, 0, 1e-12) == psm.PSM_EINVAL
     assert L.psm_set_strict_slots(None, 1) == psm.PSM_EINVAL
+    assert L.psm_set_force_readback(None, 1) == psm.PSM_EINVAL
     assert "NULL" in psm.psm_last_error() or "ctx" in psm.psm_last_error()
 
 

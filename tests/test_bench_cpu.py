@@ -56,6 +56,9 @@ class _StubEngine:
     def set_particle_velocities(self, b, U, Om=None):
         assert U.shape == (self.np[b], 3)
 
+    def set_force_readback(self, enable):
+        pass
+
     def set_equilibrium(self, b, u0):
         assert tuple(u0.shape) == (3, self.n[b])
 

@@ -104,6 +104,54 @@ def test_tile_overflow_after_integration_is_reported():
     assert np.all(np.isfinite(F))
 
 
+@pytest.mark.parametrize("readback", [False, True])
+def test_tile_overflow_after_host_upload_is_reported(readback):
+    """The same gathering uploaded by the host right after a step: without the
+    force read-back the force read of that step reports PSM_ECAPACITY; with
+    it, that read returns the step's forces (the copy was taken before the
+    re-binning) and the read after the next step, which ran on the cut lists,
+    reports it. The context then refuses to step until a new particle set."""
+    n = 48
+    g = np.array([(i, j, k) for i in range(5) for j in range(5) for k in range(3)], dtype=float)[:70]
+    x0 = 4.0 + g * np.array([9.0, 9.0, 14.0])
+    r = np.full(70, 1.0)
+    xg = np.tile(np.array([24.3, 24.7, 24.1]), (70, 1))
+    spec = inputs.BoxSpec(dims=(n, n, n), tau=0.7, fext=(1e-5, 0.0, 0.0), mapping=psm.PSM_MAP_LINEAR, nsub=4,
+                          x=x0, r=r, U=np.zeros((70, 3)), Om=np.zeros((70, 3)))
+    print(f"[case] overflow after host upload readback={readback}", flush=True)
+    u0 = np.zeros((3, spec.N))
+    ref = make_engine([spec], max_radius=1.0)
+    ref.set_launch(32, 8, 4, 0)
+    ref.set_equilibrium(0, u0)
+    ref.set_particles(0, x0, r, np.zeros((70, 3)))
+    ref.step(1)
+    F_ref, T_ref = ref.get_forces(0)
+    ref.close()
+    eng = make_engine([spec], max_radius=1.0)
+    eng.set_force_readback(readback)
+    eng.set_launch(32, 8, 4, 0)
+    eng.set_equilibrium(0, u0)
+    eng.set_particles(0, x0, r, np.zeros((70, 3)))
+    eng.step(1)
+    eng.set_particle_positions(0, xg)
+    if readback:
+        F, T = eng.get_forces(0)
+        assert np.array_equal(F, F_ref) and np.array_equal(T, T_ref)
+        eng.step(1)                      # cut lists: runs, results not valid
+    with pytest.raises(psm.PsmError) as ei:
+        eng.get_forces(0)
+    assert ei.value.code == psm.PSM_ECAPACITY
+    with pytest.raises(psm.PsmError) as ei:
+        eng.step(1)
+    assert ei.value.code == psm.PSM_ESTATE
+    eng.set_particles(0, x0, r, np.zeros((70, 3)))
+    eng.set_equilibrium(0, u0)
+    eng.step(1)
+    F, T = eng.get_forces(0)
+    eng.close()
+    assert np.array_equal(F, F_ref) and np.array_equal(T, T_ref)
+
+
 def test_spheres_bounce_off_walls_like_the_oracle():
     """Spheres driven into the side walls and the z faces of a closed box
     (velocity inflow, pressure outflow) bounce elastically one cell before
@@ -175,7 +223,9 @@ def test_host_coupling_with_split_updates_matches_oracle():
     enqueued (ordered after it on the stream, so the step and its force
     reduction see the old ones), the new velocities after the force
     read-back. Matches the oracle's step + integrator sequence, and the same
-    loop with one full psm_set_particles per step bit for bit."""
+    loop with one full psm_set_particles per step bit for bit; so does the
+    split loop with the force read-back at the end of each step (forces read
+    while the re-binning of the next positions may still run)."""
     spec = inputs.random_small((44, 36, 30), 5, (2.5, 4.0), seed=23, tau=0.65, fext=(1e-5, 0.0, -4e-6),
                                vamp=0.1, omamp=0.004)
     steps = 8
@@ -190,8 +240,9 @@ def test_host_coupling_with_split_updates_matches_oracle():
     inv_m, inv_I = (1.0 / m)[:, None], (1.0 / (0.4 * m * spec.r ** 2))[:, None]
     L = np.asarray(spec.dims, dtype=np.float64)
     results = []
-    for split in (True, False):
+    for split, readback in ((True, False), (False, False), (True, True)):
         eng = make_engine([spec])
+        eng.set_force_readback(readback)
         eng.set_pdfs(0, initial_f(spec))
         x, U, Om = spec.x.copy(), spec.U.copy(), spec.Om.copy()
         eng.set_particles(0, x, spec.r, U, Om)
@@ -219,8 +270,9 @@ def test_host_coupling_with_split_updates_matches_oracle():
             eng.set_particle_velocities(0, U[:-1], Om[:-1])
         assert e.value.code == psm.PSM_EINVAL
         eng.close()
-    (fs, Fs, Ts, xs, Us, Oms), (ff, Ff, Tf, *_) = results
+    (fs, Fs, Ts, xs, Us, Oms), (ff, Ff, Tf, *_), (fr, Fr, Tr, *_) = results
     assert np.array_equal(fs, ff) and np.array_equal(Fs, Ff) and np.array_equal(Ts, Tf)
+    assert np.array_equal(fs, fr) and np.array_equal(Fs, Fr) and np.array_equal(Ts, Tr)
     assert_pdfs_close(fs, f, 1e-12)
     assert_forces_close(Fs, ref.F, ref.A)
     assert_forces_close(Ts, ref.T, ref.A, lever=spec.r.max() + 1)

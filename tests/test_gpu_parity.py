@@ -92,6 +92,30 @@ def test_parity_extreme_radii(dims, tiles, npart, radii):
     test_parity_ragged_linear(dims, tiles, npart, npart > 1, radii=radii)
 
 
+@pytest.mark.parametrize("launch", [(16, 16, 1, 0), (16, 16, 2, 2), (32, 8, 4, 1)])
+def test_parity_spheres_wrapping_through_short_last_tiles(launch):
+    """Periodic axes whose last tile is short (33 = 16 + 16 + 1 and
+    41 = 16 + 16 + 9 cells at 16-cell tiles), with spheres whose cell range
+    wraps through that tile and so touches one tile more than a range of the
+    same length that does not wrap: each sphere's force partials, one per
+    tile it touches, must stay inside its own slots."""
+    x = np.array([[32.3, 20.0, 13.0], [32.3, 3.5, 15.5], [0.4, 0.6, 24.0], [10.0, 10.0, 25.5],
+                  [31.6, 39.7, 9.0]])
+    r = np.array([4.0, 4.0, 3.2, 2.5, 3.9])
+    rng = np.random.default_rng(7)
+    spec = inputs.BoxSpec(dims=(33, 41, 26), tau=0.7, fext=(2e-5, -1e-5, 5e-6), x=x, r=r,
+                          U=rng.uniform(-0.01, 0.01, (5, 3)), Om=rng.uniform(-0.002, 0.002, (5, 3)))
+    _print_case("short last tiles", launch=launch)
+    steps = 10
+    ref = run_oracle(spec, steps)
+    f, F, T, B, pid, eng = run_engine(spec, steps, launch=launch)
+    eng.close()
+    assert_pdfs_close(f, ref.f, 1e-12)
+    assert np.array_equal(pid, ref.pid)
+    assert_forces_close(F, ref.F, ref.A)
+    assert_forces_close(T, ref.T, ref.A, lever=r.max() + 1)
+
+
 def test_parity_no_particles_with_force():
     spec = inputs.random_small((48, 20, 12), 0, (2, 3), seed=3, tau=0.83, fext=(1e-5, 2e-6, -3e-6))
     ref = run_oracle(spec, 30)

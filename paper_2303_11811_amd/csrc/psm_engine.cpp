@@ -975,6 +975,8 @@ extern "C" int psm_step(psm_ctx* c, int nsteps) {
     if (!c) return fail(PSM_EINVAL, "ctx is NULL");
     if (nsteps < 0) return fail(PSM_EINVAL, "nsteps < 0");
     if (!c->have_particles_lists) return fail(PSM_ESTATE, "tile lists are not built");
+    // graph replays enqueue steps without passing through enqueue_step
+    if (nsteps > 0) c->rb_valid = false;
     int left = nsteps;
     if (c->use_graph && !c->timing) {
         while (left >= kGraphSteps) {
@@ -1189,6 +1191,8 @@ extern "C" int psm_run(psm_ctx* c, int nsteps, double dt, int scheme) {
     int rc = check_dynamics_args(c, dt, scheme);
     if (rc) return rc;
     if (nsteps < 0) return fail(PSM_EINVAL, "nsteps < 0");
+    // graph replays enqueue steps without passing through enqueue_step
+    if (nsteps > 0) c->rb_valid = false;
     int left = nsteps;
     if (c->use_graph && !c->timing) {
         while (left >= kGraphSteps) {

@@ -104,6 +104,37 @@ def test_tile_overflow_after_integration_is_reported():
     assert np.all(np.isfinite(F))
 
 
+def test_force_readback_follows_graph_replays():
+    """With the force read-back on, psm_get_forces after psm_step and after
+    psm_run (graph replays of step + update pairs, and eager ones) returns
+    the forces of the last step, as without it, bit for bit."""
+    spec = inputs.random_small((40, 36, 28), 4, (2.5, 4.0), seed=31, tau=0.7, fext=(1e-5, 0.0, -4e-6),
+                               vamp=0.05, omamp=0.002)
+    print("[case] force read-back after graph replays", flush=True)
+    out = []
+    for readback in (False, True):
+        eng = make_engine([spec])
+        eng.set_force_readback(readback)
+        eng.set_graph(True)
+        eng.set_pdfs(0, initial_f(spec))
+        eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
+        eng.set_dynamics(0, 2.0)
+        res = []
+        eng.step(1)
+        res.append(eng.get_forces(0))
+        eng.run(10, 1.0, psm.PSM_EULER)      # one graph replay
+        res.append(eng.get_forces(0))
+        eng.run(3, 1.0, psm.PSM_EULER)       # eager steps
+        res.append(eng.get_forces(0))
+        eng.step(10)                         # graph replay of plain steps
+        res.append(eng.get_forces(0))
+        eng.close()
+        out.append(res)
+    for (Fa, Ta), (Fb, Tb) in zip(*out):
+        assert np.array_equal(Fa, Fb) and np.array_equal(Ta, Tb)
+    assert not np.array_equal(out[1][0][0], out[1][1][0])
+
+
 @pytest.mark.parametrize("readback", [False, True])
 def test_tile_overflow_after_host_upload_is_reported(readback):
     """The same gathering uploaded by the host right after a step: without the

@@ -21,7 +21,8 @@
  *   on the device, a third sphere overlapping a cell) sets a device error
  *   word that the next synchronising call of the context (psm_get_forces,
  *   psm_get_stats, psm_get_particles) reports and clears; the kernels stay in
- *   bounds meanwhile.
+ *   bounds meanwhile. (With the force read-back on, psm_get_forces reports the
+ *   word as the step's copy saw it; see psm_set_force_readback.)
  * - Lattice units: dx = dt = 1, rho_0 = 1, c_s^2 = 1/3. Boxes are periodic
  *   along every axis without walls (psm_box_desc.walls_x, walls_y, walls_z).
  * - Cells: index n = x + nx*(y + ny*z); cell (i,j,k) has its centre at

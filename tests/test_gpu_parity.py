@@ -144,13 +144,29 @@ def test_batched_boxes_match_single_runs():
         if s.n_particles:
             eng.set_particles(b, s.x, s.r, s.U, s.Om)
     eng.step(9)
+    forces = {}
     for b, s in enumerate(specs):
         ref = run_oracle(s, 9)
         assert_pdfs_close(eng.get_pdfs(b).cpu().numpy(), ref.f, 1e-12)
         if s.n_particles:
             F, T = eng.get_forces(b)
+            forces[b] = (F, T)
             assert_forces_close(F, ref.F, ref.A)
             assert_forces_close(T, ref.T, ref.A, lever=s.r.max() + 1)
+    eng.close()
+    # the same run with the force read-back: each box's forces from the one
+    # copy of all boxes' sums that the step makes, bit for bit
+    eng = make_engine(specs)
+    eng.set_force_readback(True)
+    for b, s in enumerate(specs):
+        eng.set_pdfs(b, initial_f(s))
+        if s.n_particles:
+            eng.set_particles(b, s.x, s.r, s.U, s.Om)
+    eng.step(9)
+    for b, (F, T) in forces.items():
+        Fr, Tr = eng.get_forces(b)
+        assert np.array_equal(F, Fr) and np.array_equal(T, Tr)
+    eng.close()
 
 
 def test_graph_replay_equals_eager_bitwise():

@@ -54,11 +54,16 @@ def _triple_overlap_spec():
                           x=x, r=r, U=U, Om=np.zeros_like(U))
 
 
-def test_strict_slots_turn_a_third_overlap_into_an_error():
+@pytest.mark.parametrize("readback", [False, True])
+def test_strict_slots_turn_a_third_overlap_into_an_error(readback):
+    """Also with the force read-back, where the error word comes with the
+    copy the step makes."""
     spec = _triple_overlap_spec()
     f0 = initial_f(spec)
+    print(f"[case] strict slots readback={readback}", flush=True)
     # default: the third overlap is dropped and counted, the run goes on
     eng = make_engine([spec])
+    eng.set_force_readback(readback)
     eng.set_pdfs(0, f0)
     eng.set_particles(0, spec.x, spec.r, spec.U, spec.Om)
     eng.step(2)

@@ -181,7 +181,8 @@ int psm_get_forces(psm_ctx* ctx, int box, double* F, double* T);
 /* Force read-back for a host that integrates the spheres (the per-step
  * force transfer to the host of Sec. 3.2). enable != 0: every psm_step ends
  * by copying the force and torque sums of all boxes and the device error word
- * into pinned host memory (one copy of 48 B per sphere slot); psm_get_forces
+ * into pinned host memory (one copy, 48 B per sphere the context can hold,
+ * i.e. max_particles summed over the boxes); psm_get_forces
  * then waits for that copy only, so that a position upload and its re-binning
  * enqueued after the step run while the host reads the forces and updates
  * the velocities. The error word is the one the copy saw: an overflow raised

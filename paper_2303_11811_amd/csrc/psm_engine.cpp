@@ -65,9 +65,8 @@ static bool shape_allowed(int tx, int ty, int tz) {
 static int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 // Largest number of tiles the bounding box [x-(r+1), x+(r+1)] can touch along
-// an axis of L cells cut into tiles of T cells.
-// Most tiles of one axis that a sphere's cell range can touch. The range
-// spans at most E = floor(2(r+1)) + 2 cells. On a periodic axis whose last
+// an axis of L cells cut into tiles of T cells. Its cell range spans at most
+// E = floor(2(r+1)) + 2 cells. On a periodic axis whose last
 // tile is short (r_last = L - (nt-1)T cells), a range that wraps through it
 // touches 1 + ceil((a - r_last)/T) tiles before the wrap and ceil((E - a)/T)
 // after it (a cells before the wrap), at most 2 + ceil((E - r_last)/T) in
